@@ -1,0 +1,293 @@
+/*
+ * dbas_mppi.h -- C ABI of the MI355X (gfx950) DBaS-Log-MPPI library.
+ *
+ * One call of mppi_step runs one iteration of the sampling-based controller of
+ * Yin et al., "DBaS-Log-MPPI: Efficient and Safe Trajectory Optimization via
+ * Barrier States": draw K normal x log-normal perturbation sequences of
+ * horizon T (Sec. IV-C), roll the barrier-state-augmented dynamics out for
+ * every sample while accumulating the cost-to-go (Sec. IV-A, eq.
+ * cost-to-go_bas; Algorithm 1), form the min-shifted exponential weights and
+ * the weighted-average update of the control sequence (Sec. III-A, eq.
+ * control_update), hand u0* out and shift the warm start (Algorithm 1, closing
+ * loop).  The adaptive exploration rate S_e (Sec. IV-B, eq. scaling factor) is
+ * an input.
+ *
+ * Conventions for every call:
+ *  - Plain C types only.  Pointers are host pointers unless the argument says
+ *    "device" or a `mem` argument selects MPPI_MEM_DEVICE.
+ *  - The library copies whatever it keeps; the caller owns its buffers and may
+ *    free them when the call returns (for *_async calls: once the stream work
+ *    has completed).
+ *  - Every call returns an mppi_status (or void for destroy).  No exception or
+ *    abort crosses the ABI.  After an error, mppi_last_error(handle) describes
+ *    it.  A device error (MPPI_E_DEVICE) poisons the handle: every later call on
+ *    it returns MPPI_E_DEVICE.
+ *  - A handle is not thread-safe; distinct handles may be used from distinct
+ *    threads.
+ *
+ * Layouts:  states are float[n] with n = 6 (QUAD6: x, z, theta, vx, vz,
+ * omega), 5 (QUAD5: x, z, theta, vx, vz) or 4 (CAR: x, y, theta, v).  Every
+ * model has m = 2 inputs: QUAD6 (thrust deviation of rotor 1, rotor 2) from
+ * hover, QUAD5 (pitch rate, throttle), CAR (steering angle, acceleration).
+ * Control sequences are float[T][2] row-major; references float[T+1][n].
+ */
+#ifndef DBAS_MPPI_H
+#define DBAS_MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_ABI_VERSION 1u
+#define MPPI_M 2          /* inputs per model */
+#define MPPI_NMAX 6       /* largest state dimension */
+#define MPPI_PMAX 16      /* most body shape points */
+#define MPPI_JMAX 2048    /* most circular obstacles per controller */
+#define MPPI_TMAX 1024    /* longest horizon */
+#define MPPI_KMAX 262144  /* most samples */
+
+typedef enum {
+    MPPI_OK = 0,
+    MPPI_E_INVALID = 1,   /* bad argument or configuration; nothing was launched */
+    MPPI_E_NOMEM = 2,     /* a device or pinned-host allocation failed */
+    MPPI_E_DEVICE = 3,    /* a HIP call failed; the handle is poisoned */
+    MPPI_E_NUMERIC = 4,   /* no sample had a finite cost; U and the counter are unchanged */
+    MPPI_E_BUSY = 5       /* (server) result not ready yet / no capacity */
+} mppi_status;
+
+typedef enum { MPPI_QUAD6 = 0, MPPI_QUAD5 = 1, MPPI_CAR = 2 } mppi_model;
+typedef enum { MPPI_NORM_AUTO = 0, MPPI_NORM_ON = 1, MPPI_NORM_OFF = 2 } mppi_normaliser;
+typedef enum { MPPI_INIT_REPEAT = 0, MPPI_INIT_ZERO = 1 } mppi_init_mode;
+typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
+
+/*
+ * Problem statement (Sec. III-A eq. mppi; Algorithm 1's Require list; Sec.
+ * IV-B/IV-C sampling parameters; Sec. V-A/V-B models, limits, shape points).
+ *  - sigma[c]: standard deviation of channel c, Sigma_u = diag(sigma^2); a
+ *    channel with sigma = 0 is not sampled and carries no control cost.
+ *  - Noise: du = sqrt(S_e) sigma_c n exp(mu_ln + sigma_ln z) with n, z
+ *    independent standard normals (Sec. IV-C mixture, scaled per Alg. 1).
+ *  - lambda > 0: temperature of exp(-(S - rho)/lambda).
+ *  - gamma_u: control-cost weight of gamma_u U_t^T S_e^-1 Sigma_u^-1 v_t.
+ *  - gamma_b in (0,1): barrier-state relaxation of eq. barrier_update.
+ *  - r_b: R_B, weight of the barrier state in the running cost.
+ *  - h_eps > 0: the barrier is B(h) = 1/max(h, h_eps).
+ *  - Q, Qf: diagonal running and terminal weights on (x - x_ref).
+ *  - shape[P][2]: body-frame shape points (along the heading, normal to it).
+ *  - u_min/u_max: actuator limits, applied inside the dynamics.
+ *  - tile_lanes: lanes that share one sample's obstacle loop (1, 2, 4, 8 or
+ *    16); 0 lets the autotuner choose (per model, K, T, J, P).
+ */
+typedef struct mppi_config {
+    uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
+    int32_t model;                 /* mppi_model */
+    int32_t K, T;                  /* samples (1..MPPI_KMAX), horizon (1..MPPI_TMAX) */
+    float dt;
+    float mass, gravity, arm, inertia, wheelbase;
+    float u_min[MPPI_M], u_max[MPPI_M];
+    float sigma[MPPI_M];
+    float mu_ln, sigma_ln;
+    float lambda, gamma_u, gamma_b, r_b, h_eps;
+    float Q[MPPI_NMAX], Qf[MPPI_NMAX];
+    int32_t P;
+    float shape[MPPI_PMAX][2];
+    uint64_t seed;                 /* Philox key */
+    int32_t normaliser;            /* mppi_normaliser */
+    int32_t init_mode;             /* mppi_init_mode */
+    int32_t tile_lanes;            /* 0 = autotune */
+    int32_t reserved[7];           /* must be zero */
+} mppi_config;
+
+/* Where a handle runs.  stream: a hipStream_t owned by the caller (NULL: the
+ * library creates its own, at default priority). */
+typedef struct mppi_device {
+    int32_t device;
+    void* stream;
+} mppi_device;
+
+/* Checkpointable controller state: warm start U[T][2], Philox step counter,
+ * exploration rate. */
+typedef struct mppi_state {
+    uint64_t counter;
+    float S_e;
+    int32_t T;
+    float* U;                      /* host, T*2 floats, caller-allocated */
+} mppi_state;
+
+/* What the last completed iteration produced. */
+typedef struct mppi_step_info {
+    uint64_t counter;              /* counter the iteration's noise used */
+    int32_t status;                /* mppi_status of the iteration */
+    int32_t fp64_tiles;            /* sample tiles whose weights ran in FP64 */
+    double rho;                    /* min_k S_k */
+    double eta;                    /* sum_k exp(-(S_k - rho)/lambda) */
+    float beta0;                   /* fused barrier at x0 */
+    float beta_d;                  /* fused barrier at x_d = x_ref[T] */
+    int32_t tile_lanes;            /* lanes per sample used */
+    int32_t tiles;                 /* sample tiles per iteration */
+} mppi_step_info;
+
+typedef struct mppi_ctrl mppi_t;
+
+/* Fill *cfg with the defaults of `model` (the paper's limits, mass, frame,
+ * inertia and shape points; sigma 0.5; lambda 1; gamma_u 2; gamma_b 0.5;
+ * R_B 0.1; h_eps 1e-4; mu_ln 0, sigma_ln 0.3; Q as in the test workloads). */
+int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_config* cfg);
+
+/* Create a controller.  Allocates every device buffer it needs (sized by K, T)
+ * and copies the configuration.  U starts at zero, counter at 0, S_e at 1, no
+ * obstacles, no costmap, a zero reference.  Errors: INVALID (bad config),
+ * NOMEM, DEVICE. */
+int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_t** out);
+
+/* Free everything (NULL-safe).  Waits for the handle's pending work. */
+void mppi_destroy(mppi_t* h);
+
+/* Circular obstacles (Sec. V-A/V-B: h = |p - c|^2 - r^2): J rows of
+ * (cx, cy, r), copied.  J = 0 clears them.  Errors: INVALID (J outside
+ * 0..MPPI_JMAX, non-finite or negative r). */
+int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int32_t mem);
+
+/* Optional signed-distance costmap, row-major sdf[H][W] in metres, cell
+ * (col i, row j) centred at (x0 + (i+1/2) res, y0 + (j+1/2) res), sampled
+ * bilinearly and clamped to the edge; each shape point adds B(sdf) to the
+ * fused barrier.  sdf = NULL clears it.  Errors: INVALID (W or H < 2, res <= 0). */
+int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float y0, float res,
+                     const float* sdf, int32_t mem);
+
+/* Reference x_ref[T+1][n] for the running cost (step t uses x_ref[t+1]) and
+ * the terminal cost (x_ref[T]); the desired equilibrium of eq.
+ * barrier_update is x_d = x_ref[T]. */
+int mppi_set_reference(mppi_t* h, const float* x_ref, int32_t mem);
+
+/* Exploration rate S_e > 0 (Sec. IV-B); it scales the noise variance and
+ * divides the control cost. */
+int mppi_set_exploration(mppi_t* h, float S_e);
+
+/* Overwrite the warm start U[T][2]. */
+int mppi_set_controls(mppi_t* h, const float* U, int32_t mem);
+
+/* One iteration from state x0 (host float[n]); writes u0* (host float[2]) and
+ * blocks until it is available.  Errors: INVALID (non-finite x0), NUMERIC
+ * (every cost non-finite: U and counter unchanged, u0 = current U[0]), DEVICE. */
+int mppi_step(mppi_t* h, const float* x0, float* u0);
+
+/* Stream-ordered iteration: x0 is a device float[n]; u0 (device float[2], may
+ * be NULL) is written when the iteration completes.  Does not block.  The
+ * iteration's status is read by mppi_synchronize or mppi_get_step_info. */
+int mppi_step_async(mppi_t* h, const float* x0_device, float* u0_device);
+
+/* Wait for the handle's stream; returns the status of the last iteration. */
+int mppi_synchronize(mppi_t* h);
+
+/* Inspection (host buffers, caller-allocated; each waits for the stream). */
+int mppi_get_controls(mppi_t* h, float* U);              /* warm start, T*2 */
+int mppi_get_last_optimal(mppi_t* h, float* Ustar);      /* U* before the shift, T*2 */
+int mppi_get_costs(mppi_t* h, double* S);                /* S_k, K (compensated sum as FP64) */
+int mppi_get_weights(mppi_t* h, double* w);              /* normalised weights, K */
+int mppi_get_noise(mppi_t* h, float* du);                /* du[k][t][c], K*T*2 */
+int mppi_get_step_info(mppi_t* h, mppi_step_info* info);
+/* Raw Philox4x32-10 words of every (k, t) for the given counter:
+ * words[(k*T + t)*4 + i], from the same device function the sampler uses. */
+int mppi_get_philox_words(mppi_t* h, uint64_t counter, uint32_t* words);
+
+/* Checkpoint / resume: a restored controller continues bit-identically. */
+int mppi_get_state(mppi_t* h, mppi_state* st);
+int mppi_set_state(mppi_t* h, const mppi_state* st);
+
+const char* mppi_last_error(const mppi_t* h);
+const char* mppi_status_string(int32_t status);
+
+/* The stream (hipStream_t) a handle launches on. */
+void* mppi_stream(const mppi_t* h);
+
+/* Kernel timing.  With profiling on, every later iteration records HIP events
+ * on the handle's stream around its rollout kernel and its update kernel.
+ * mppi_profile_read waits for the stream, returns the totals over the
+ * iterations recorded since the last read, and clears them.  Turning it on
+ * allocates events (up to 4096 iterations are kept; later ones are dropped
+ * and counted in `dropped`). */
+typedef struct mppi_profile {
+    int64_t iterations;
+    int64_t dropped;
+    double rollout_ms;             /* summed rollout-kernel durations */
+    double update_ms;              /* summed update-kernel durations */
+} mppi_profile;
+
+int mppi_profile_enable(mppi_t* h, int32_t on);
+int mppi_profile_read(mppi_t* h, mppi_profile* out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched iteration: many controllers (any mix of models, K, T, J) stepped  */
+/* by one persistent kernel, captured once in a HIP graph.  Controllers stay */
+/* owned by the caller and must outlive the batch; each one's tile shape is   */
+/* its own (autotuned per model, K, T, J), so a controller's result is the    */
+/* same alone and in the batch.                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct mppi_batch mppi_batch_t;
+
+int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_device* dev, mppi_batch_t** out);
+void mppi_batch_destroy(mppi_batch_t* b);
+/* x0s: host float[n][MPPI_NMAX] (row c holds controller c's state); u0s: host
+ * float[n][2]; statuses (nullable): host int32[n].  Blocks.  Returns MPPI_OK
+ * when every controller succeeded, else the first failing status. */
+int mppi_batch_step(mppi_batch_t* b, const float* x0s, float* u0s, int32_t* statuses);
+const char* mppi_batch_last_error(const mppi_batch_t* b);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: robots submit control-step requests; a scheduler thread admits   */
+/* them while launch slots and the device-memory budget allow, and batches   */
+/* whatever is admitted into the next launch on one of several streams       */
+/* (continuous batching).  Each robot keeps its warm start, Philox counter,  */
+/* obstacles and reference resident on the device; requests of one robot run */
+/* in submission order.                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct mppi_server mppi_server_t;
+
+typedef struct mppi_server_config {
+    uint32_t abi_version;
+    int32_t device;
+    int64_t budget_bytes;          /* device bytes for in-flight sample scratch */
+    int32_t max_slots;             /* most requests in flight */
+    int32_t streams;               /* launch streams (>= 1) */
+    int32_t max_batch;             /* most requests per launch */
+    int32_t reserved[7];
+} mppi_server_config;
+
+typedef struct mppi_server_stats {
+    int64_t submitted, completed, launches, deferred_budget, deferred_slots;
+    int64_t peak_bytes_in_flight;
+    double mean_batch;
+} mppi_server_stats;
+
+int mppi_server_create(const mppi_server_config* cfg, mppi_server_t** out);
+void mppi_server_destroy(mppi_server_t* s);
+/* Register a robot.  The configuration, obstacles and costmap are copied into
+ * server-owned device state.  id receives the robot index. */
+int mppi_server_add_robot(mppi_server_t* s, const mppi_config* cfg, int32_t J, const float* cxcyr,
+                          int32_t* id);
+/* Queue one control step for robot id from state x0 (host float[n]) with
+ * reference x_ref (host float[T+1][n], NULL keeps the last one).  t_arrival is
+ * the caller's timestamp in seconds (monotonic clock).  ticket receives the
+ * request handle. */
+int mppi_server_submit(mppi_server_t* s, int32_t id, const float* x0, const float* x_ref,
+                       double t_arrival, int64_t* ticket);
+/* MPPI_OK and u0 (host float[2]) once the request completed, MPPI_E_BUSY while
+ * it is pending.  latency (nullable) = completion time - t_arrival (s);
+ * status (nullable) = the iteration's own status. */
+int mppi_server_poll(mppi_server_t* s, int64_t ticket, float* u0, double* latency, int32_t* status);
+/* Block until the request completed, then as poll. */
+int mppi_server_wait(mppi_server_t* s, int64_t ticket, float* u0, double* latency, int32_t* status);
+/* Monotonic clock of the server (s), for t_arrival. */
+double mppi_server_now(const mppi_server_t* s);
+int mppi_server_get_stats(mppi_server_t* s, mppi_server_stats* st);
+/* Read back a robot's warm start U[T][2] and counter (for tests). */
+int mppi_server_get_robot(mppi_server_t* s, int32_t id, float* U, uint64_t* counter);
+const char* mppi_server_last_error(const mppi_server_t* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

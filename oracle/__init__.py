@@ -88,14 +88,16 @@ def lib():
         L.orc_sdf_lookup.restype = ctypes.c_double
         L.orc_fused_barrier.argtypes = [cp, wp, dp]
         L.orc_fused_barrier.restype = ctypes.c_double
-        L.orc_rollout_one.argtypes = [cp, wp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_rollout_one.argtypes = [cp, wp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_rollout_one.restype = ctypes.c_double
+        L.orc_clearance.argtypes = [cp, wp, dp]
+        L.orc_clearance.restype = ctypes.c_double
         L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
         L.orc_weights.restype = ctypes.c_int
         L.orc_update.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_shift.argtypes = [cp, dp, dp]
         L.orc_step.argtypes = [cp, wp, dp, dp, dp, ctypes.c_double, ctypes.c_uint64,
-                               dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+                               dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_step.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -233,16 +235,27 @@ def fused_barrier(params: dict, world: World, x) -> float:
     return lib().orc_fused_barrier(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x))
 
 
-def rollout_one(params: dict, world: World, x0, U, du_k, x_ref, S_e=1.0, beta_d=0.0):
-    """Returns (S, X[(T+1), n], beta[T+1])."""
+def rollout_one(params: dict, world: World, x0, U, du_k, x_ref, S_e=1.0, beta_d=0.0, with_clearance=False):
+    """Returns (S, X[(T+1), n], beta[T+1]) (+ the smallest clearance over
+    steps 1..T and the barrier sensitivity when with_clearance)."""
     cfg = make_cfg(params)
     n = STATE_DIM[params["model"]]
     x0, U, du_k, x_ref = _f64(x0), _f64(U), _f64(du_k), _f64(x_ref)
     X = np.zeros((cfg.T + 1, n))
     beta = np.zeros(cfg.T + 1)
+    mh, sens = ctypes.c_double(), ctypes.c_double()
     S = lib().orc_rollout_one(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x0), _dp(U), _dp(du_k),
-                              _dp(x_ref), float(S_e), float(beta_d), _dp(X), _dp(beta))
+                              _dp(x_ref), float(S_e), float(beta_d), _dp(X), _dp(beta), ctypes.byref(mh),
+                              ctypes.byref(sens))
+    if with_clearance:
+        return S, X, beta, mh.value, sens.value
     return S, X, beta
+
+
+def clearance(params: dict, world: World, x) -> float:
+    cfg = make_cfg(params)
+    x = _f64(x)
+    return lib().orc_clearance(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x))
 
 
 def weights(S, lam: float):
@@ -282,9 +295,12 @@ def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int) -> 
     Ustar = np.zeros((T, 2))
     Unext = np.zeros((T, 2))
     u0 = np.zeros(2)
+    clear = np.zeros(K)
+    sens = np.zeros(K)
     sc = [ctypes.c_double() for _ in range(4)]
     st = lib().orc_step(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x0), _dp(U), _dp(x_ref),
                         float(S_e), int(counter), _dp(du), _dp(S), _dp(w), _dp(Ustar), _dp(Unext),
-                        _dp(u0), *[ctypes.byref(s) for s in sc])
+                        _dp(u0), *[ctypes.byref(s) for s in sc], _dp(clear), _dp(sens))
     return {"status": st, "du": du, "S": S, "w": w, "Ustar": Ustar, "Unext": Unext, "u0": u0,
-            "rho": sc[0].value, "eta": sc[1].value, "beta0": sc[2].value, "beta_d": sc[3].value}
+            "rho": sc[0].value, "eta": sc[1].value, "beta0": sc[2].value, "beta_d": sc[3].value,
+            "clear": clear, "sens": sens}

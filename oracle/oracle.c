@@ -212,6 +212,56 @@ double orc_fused_barrier(const orc_cfg* cfg, const orc_world* w, const double* x
     return sum;
 }
 
+/* Clearance of state x: the smallest h over all shape points and constraints
+ * (INFINITY when there is none).  A diagnostic for the comparison tolerance,
+ * not part of the controller. */
+double orc_clearance(const orc_cfg* cfg, const orc_world* w, const double* x)
+{
+    double pts[2 * ORC_PMAX];
+    orc_shape_points(cfg, x, pts);
+    double m = INFINITY;
+    for (int i = 0; i < cfg->P; ++i) {
+        for (int j = 0; j < w->J; ++j) {
+            double dx = pts[2 * i] - w->obs[3 * j];
+            double dy = pts[2 * i + 1] - w->obs[3 * j + 1];
+            double r = w->obs[3 * j + 2];
+            double h = dx * dx + dy * dy - r * r;
+            if (h < m) m = h;
+        }
+        if (w->sdf != NULL && w->map_w > 0) {
+            double h = orc_sdf_lookup(w, pts[2 * i], pts[2 * i + 1]);
+            if (h < m) m = h;
+        }
+    }
+    return m;
+}
+
+/* Sensitivity of the fused barrier at state x to a displacement of every
+ * shape point by at most 1 (metre) per coordinate: the sum over unclamped
+ * terms of |dB/dp| = sqrt(2) |dh/dp| / h^2, with |dh/dp| = 2 |p - c| for a
+ * circle and <= 1 for the costmap (a signed distance has unit gradient).
+ * A diagnostic for the comparison tolerance, not part of the controller. */
+double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x)
+{
+    double pts[2 * ORC_PMAX];
+    orc_shape_points(cfg, x, pts);
+    double s = 0.0;
+    for (int i = 0; i < cfg->P; ++i) {
+        for (int j = 0; j < w->J; ++j) {
+            double dx = pts[2 * i] - w->obs[3 * j];
+            double dy = pts[2 * i + 1] - w->obs[3 * j + 1];
+            double r = w->obs[3 * j + 2];
+            double h = dx * dx + dy * dy - r * r;
+            if (h > cfg->h_eps) s += sqrt(2.0) * 2.0 * sqrt(dx * dx + dy * dy) / (h * h);
+        }
+        if (w->sdf != NULL && w->map_w > 0) {
+            double h = orc_sdf_lookup(w, pts[2 * i], pts[2 * i + 1]);
+            if (h > cfg->h_eps) s += sqrt(2.0) / (h * h);
+        }
+    }
+    return s;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rollout of one sample (Algorithm 1, the inner loop; eq. MPPI_BaS,         */
 /* eq. barrier_update, eq. cost-to-go_bas).                                  */
@@ -226,9 +276,11 @@ double orc_fused_barrier(const orc_cfg* cfg, const orc_world* w, const double* x
 /* ------------------------------------------------------------------------ */
 double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
                        const double* U, const double* du_k, const double* x_ref,
-                       double S_e, double beta_d, double* X, double* beta_out)
+                       double S_e, double beta_d, double* X, double* beta_out, double* min_h, double* sens)
 {
     int n = orc_state_dim(cfg->model);
+    if (min_h) *min_h = INFINITY;
+    if (sens) *sens = 0.0;
     double x[ORC_NMAX], xn[ORC_NMAX];
     for (int a = 0; a < n; ++a) x[a] = x0[a];
     if (X) for (int a = 0; a < n; ++a) X[a] = x[a];
@@ -252,6 +304,13 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
         S += q + cfg->gamma_u * ctrl + cfg->r_b * beta;
         if (X) for (int a = 0; a < n; ++a) X[(size_t)(t + 1) * n + a] = x[a];
         if (beta_out) beta_out[t + 1] = beta;
+        if (min_h) {
+            double h = orc_clearance(cfg, w, x);
+            if (h < *min_h) *min_h = h;
+        }
+        /* a change db_t of the fused barrier reaches the cost through
+         * beta_t, beta_t+1, ... with weights summing to at most 1/(1-gamma_B) */
+        if (sens) *sens += cfg->r_b / (1.0 - cfg->gamma_b) * orc_barrier_sensitivity(cfg, w, x);
     }
     const double* refT = x_ref + (size_t)cfg->T * n;
     double phi = 0.0;
@@ -310,7 +369,7 @@ void orc_shift(const orc_cfg* cfg, const double* Ustar, double* Unext)
 int orc_step(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* U,
              const double* x_ref, double S_e, uint64_t counter,
              double* du_out, double* S_out, double* w_out, double* Ustar, double* Unext, double* u0,
-             double* rho, double* eta, double* beta0_out, double* beta_d_out)
+             double* rho, double* eta, double* beta0_out, double* beta_d_out, double* clear, double* sens)
 {
     int K = cfg->K, T = cfg->T, n = orc_state_dim(cfg->model);
     double* du = du_out ? du_out : (double*)malloc(sizeof(double) * (size_t)K * T * ORC_M);
@@ -324,7 +383,8 @@ int orc_step(const orc_cfg* cfg, const orc_world* w, const double* x0, const dou
 
     orc_noise(cfg, S_e, counter, du);
     for (int k = 0; k < K; ++k)
-        S[k] = orc_rollout_one(cfg, w, x0, U, du + (size_t)k * T * ORC_M, x_ref, S_e, beta_d, NULL, NULL);
+        S[k] = orc_rollout_one(cfg, w, x0, U, du + (size_t)k * T * ORC_M, x_ref, S_e, beta_d, NULL, NULL,
+                               clear ? clear + k : NULL, sens ? sens + k : NULL);
     int status = orc_weights(S, K, cfg->lambda, wt, rho, eta);
     if (status == ORC_OK) {
         orc_update(U, du, wt, K, T, Ustar);

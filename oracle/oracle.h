@@ -94,11 +94,21 @@ double orc_sdf_lookup(const orc_world* w, double px, double py);
 /* Fused barrier sum_i sum_j B(h_ij(x)) (+ sum_i B(sdf(p_i))). */
 double orc_fused_barrier(const orc_cfg* cfg, const orc_world* w, const double* x);
 
+/* Smallest h over all shape points and constraints at state x (diagnostic). */
+double orc_clearance(const orc_cfg* cfg, const orc_world* w, const double* x);
+
+/* Sum over unclamped barrier terms at x of |dB/dp| for a unit displacement of
+ * every shape point (diagnostic). */
+double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x);
+
 /* Rollout of one sample.  Returns its cost S.  Optional outputs:
- * X[(T+1)*n] states, beta[T+1] barrier states (beta[0] = beta_0). */
+ * X[(T+1)*n] states, beta[T+1] barrier states (beta[0] = beta_0), min_h the
+ * smallest clearance over steps 1..T, sens the bound on |dS| per metre of
+ * shape-point displacement through the barrier (diagnostics for comparison
+ * tolerances). */
 double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
                        const double* U, const double* du_k, const double* x_ref,
-                       double S_e, double beta_d, double* X, double* beta);
+                       double S_e, double beta_d, double* X, double* beta, double* min_h, double* sens);
 
 /* Min-shifted exponential weights.  Returns ORC_OK or ORC_NUMERIC. */
 int orc_weights(const double* S, int K, double lambda, double* w, double* rho, double* eta);
@@ -110,11 +120,13 @@ void orc_update(const double* U, const double* du, const double* w, int K, int T
 void orc_shift(const orc_cfg* cfg, const double* Ustar, double* Unext);
 
 /* One full iteration.  All outputs caller-allocated (any may be NULL except
- * Ustar/Unext/u0).  Returns ORC_OK or ORC_NUMERIC (then Ustar = Unext = U). */
+ * Ustar/Unext/u0).  Returns ORC_OK or ORC_NUMERIC (then Ustar = Unext = U).
+ * clear[K], sens[K] (optional): each sample's smallest clearance and barrier
+ * sensitivity over its rollout (see orc_rollout_one). */
 int orc_step(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* U,
              const double* x_ref, double S_e, uint64_t counter,
              double* du, double* S, double* wts, double* Ustar, double* Unext, double* u0,
-             double* rho, double* eta, double* beta0, double* beta_d);
+             double* rho, double* eta, double* beta0, double* beta_d, double* clear, double* sens);
 
 #ifdef __cplusplus
 }

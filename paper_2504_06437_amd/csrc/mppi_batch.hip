@@ -1,0 +1,316 @@
+// Batched iteration of many controllers in one persistent launch, captured
+// once into a HIP graph, plus the per-shape tile autotuner and the library's
+// global error slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mppi_internal.hpp"
+#include "mppi_runtime.hpp"
+
+using namespace dbas;
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_global_error(const std::string& s) { g_error = s; }
+const char* global_error() { return g_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Autotuner: lanes per sample G for a (model, K, T, J, P) shape.  Candidates
+// are timed on the controller's own data with scratch outputs; the choice is
+// cached per shape for the process, so every controller of one shape (alone
+// or in a batch) runs the same tile shape.
+// ---------------------------------------------------------------------------
+namespace {
+
+using ShapeKey = std::tuple<int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<ShapeKey, int> g_tune_cache;
+
+bool autotune_enabled()
+{
+    const char* v = std::getenv("MPPI_AUTOTUNE");
+    return !(v && v[0] == '0');
+}
+
+// Time the rollout kernel of `h` with G lanes per sample; returns ms or -1.
+float time_rollout(mppi_ctrl* h, int G, int reps)
+{
+    DevParams q = h->p;
+    q.G = G;
+    q.spt = kBlock / G;
+    q.tiles = (q.K + q.spt - 1) / q.spt;
+    const size_t tiles = (size_t)q.tiles;
+    void* buf = nullptr;
+    const size_t bytes = sizeof(CtrlState) + sizeof(float) * ((size_t)q.T * kM * q.Kp + 3 * (size_t)q.Kp) +
+                         sizeof(double) * (3 * tiles + 2 * (size_t)q.T * tiles) + sizeof(int32_t) * tiles + 256;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0f;
+    }
+    char* c = static_cast<char*>(buf);
+    auto take = [&](size_t n) {
+        char* r = c;
+        c += (n + 15) & ~(size_t)15;
+        return r;
+    };
+    q.st = reinterpret_cast<CtrlState*>(take(sizeof(CtrlState)));
+    q.du = reinterpret_cast<float*>(take(sizeof(float) * (size_t)q.T * kM * q.Kp));
+    q.S = reinterpret_cast<float*>(take(sizeof(float) * 2 * (size_t)q.Kp));
+    q.e = reinterpret_cast<float*>(take(sizeof(float) * (size_t)q.Kp));
+    q.rho_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
+    q.eta_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
+    q.f_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
+    q.flag_b = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * tiles));
+    q.partN = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)q.T * tiles));
+    q.res = nullptr;
+    float best = -1.0f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipMemcpyAsync(q.st, h->p.st, sizeof(CtrlState), hipMemcpyDeviceToDevice, h->stream) == hipSuccess &&
+              hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int r = 0; ok && r <= reps; ++r) {
+        // keep the copy's ticket and iteration parity where the real state has them
+        ok = hipMemcpyAsync(q.st, h->p.st, sizeof(CtrlState), hipMemcpyDeviceToDevice, h->stream) == hipSuccess;
+        ok = ok && hipEventRecord(e0, h->stream) == hipSuccess;
+        ok = ok && launch_rollout(q, a, h->stream) == hipSuccess;
+        ok = ok && hipEventRecord(e1, h->stream) == hipSuccess;
+        ok = ok && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (ok && r > 0 && (best < 0 || ms < best)) best = ms;   // r = 0 warms up
+    }
+    if (!ok) (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(buf);
+    return ok ? best : -1.0f;
+}
+
+}  // namespace
+
+namespace dbas {
+
+int choose_tile_lanes(mppi_ctrl* h)
+{
+    const DevParams& p = h->p;
+    const ShapeKey key{p.model, p.K, p.T, p.J, p.P, p.sdf != nullptr ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    int G = heuristic_tile_lanes(p.K, p.J);
+    if (autotune_enabled() && p.J > 0 && h->sync() == MPPI_OK) {
+        float best = -1.0f;
+        for (int cand : {1, 2, 4, 8, 16}) {
+            const float ms = time_rollout(h, cand, 3);
+            if (ms > 0 && (best < 0 || ms < best * 0.97f)) {
+                best = ms;
+                G = cand;
+            }
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.emplace(key, G);
+    return g_tune_cache[key];
+}
+
+}  // namespace dbas
+
+// ---------------------------------------------------------------------------
+// Batch
+// ---------------------------------------------------------------------------
+struct mppi_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<mppi_ctrl*> ctrls;
+    std::vector<uint64_t> versions;
+    std::vector<DevParams> params;
+    DevParams* d_params = nullptr;
+    BatchUnit* d_units = nullptr;
+    RowUnit* d_rows = nullptr;
+    uint32_t* d_queue = nullptr;
+    float* d_x0s = nullptr;
+    float* h_x0s = nullptr;        // pinned staging of the per-step states
+    int nunits = 0, nrows = 0, grid = 0;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+
+    ~mppi_batch()
+    {
+        (void)hipSetDevice(device);
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void* p : {(void*)d_params, (void*)d_units, (void*)d_rows, (void*)d_queue, (void*)d_x0s})
+            if (p) (void)hipFree(p);
+        if (h_x0s) (void)hipHostFree(h_x0s);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    int fail(int st, const std::string& s)
+    {
+        err = s;
+        return st;
+    }
+
+    int hip(hipError_t e, const char* what)
+    {
+        if (e == hipSuccess) return MPPI_OK;
+        (void)hipGetLastError();
+        return fail(MPPI_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+
+    // (Re)build the work lists and the graph from the controllers' current shapes.
+    int build()
+    {
+        const int n = (int)ctrls.size();
+        params.resize(n);
+        versions.resize(n);
+        std::vector<std::pair<double, BatchUnit>> work;
+        std::vector<RowUnit> rows;
+        size_t lds_max = 0;
+        for (int c = 0; c < n; ++c) {
+            params[c] = ctrls[c]->p;
+            versions[c] = ctrls[c]->version;
+            const DevParams& p = params[c];
+            lds_max = std::max(lds_max, tile_lds_bytes(p.J, p.T, p.n));
+            // longest-processing-time order: per-tile work ~ samples x steps x (pairs + fixed)
+            const double cost = (double)std::min(p.spt, p.K) * p.T * ((double)p.P * p.J / p.G + 64.0);
+            for (int t = 0; t < p.tiles; ++t) work.push_back({cost, BatchUnit{c, t}});
+            for (int r = 0; r < 2 * p.T; r += kRowsPerBlock) rows.push_back(RowUnit{c, r});
+        }
+        std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        std::vector<BatchUnit> units(work.size());
+        for (size_t i = 0; i < work.size(); ++i) units[i] = work[i].second;
+        nunits = (int)units.size();
+        nrows = (int)rows.size();
+        lds = lds_max;
+
+        int st;
+        if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+        if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+        for (void** p : {(void**)&d_params, (void**)&d_units, (void**)&d_rows})
+            if (*p) { (void)hipFree(*p); *p = nullptr; }
+        if ((st = hip(hipMalloc(&d_params, sizeof(DevParams) * n), "hipMalloc params"))) return st;
+        if ((st = hip(hipMalloc(&d_units, sizeof(BatchUnit) * nunits), "hipMalloc units"))) return st;
+        if ((st = hip(hipMalloc(&d_rows, sizeof(RowUnit) * nrows), "hipMalloc rows"))) return st;
+        if ((st = hip(hipMemcpy(d_params, params.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice), "params"))) return st;
+        if ((st = hip(hipMemcpy(d_units, units.data(), sizeof(BatchUnit) * nunits, hipMemcpyHostToDevice), "units"))) return st;
+        if ((st = hip(hipMemcpy(d_rows, rows.data(), sizeof(RowUnit) * nrows, hipMemcpyHostToDevice), "rows"))) return st;
+
+        int cus = 0;
+        if ((st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "CU count"))) return st;
+        grid = std::max(1, std::min(nunits, cus * batch_rollout_blocks_per_cu(lds)));
+
+        // capture: states H2D, persistent rollout, row update
+        if ((st = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture"))) return st;
+        hipError_t e = hipMemcpyAsync(d_x0s, h_x0s, sizeof(float) * (MPPI_NMAX + 2) * n, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_batch_rollout(d_params, d_units, nunits, d_x0s, d_queue, grid, lds, stream);
+        if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, nullptr, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(stream, &g);
+        if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip(e, "captured launch"); }
+        if ((st = hip(e2, "end capture"))) return st;
+        graph = g;
+        return hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    }
+};
+
+extern "C" int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_device* dev, mppi_batch_t** out)
+{
+    if (!out || !ctrls || n < 1) return MPPI_E_INVALID;
+    *out = nullptr;
+    mppi_batch* b = new (std::nothrow) mppi_batch();
+    if (!b) return MPPI_E_NOMEM;
+    b->device = dev ? dev->device : 0;
+    for (int c = 0; c < n; ++c) {
+        if (!ctrls[c] || ctrls[c]->poisoned || ctrls[c]->device != b->device) {
+            set_global_error("mppi_batch_create: controllers must be valid handles on the batch's device");
+            delete b;
+            return MPPI_E_INVALID;
+        }
+        b->ctrls.push_back(ctrls[c]);
+    }
+    int st = MPPI_OK;
+    if (!st) st = b->hip(hipSetDevice(b->device), "hipSetDevice");
+    if (!st && dev && dev->stream) b->stream = static_cast<hipStream_t>(dev->stream);
+    else if (!st) {
+        st = b->hip(hipStreamCreate(&b->stream), "hipStreamCreate");
+        b->own_stream = true;
+    }
+    for (mppi_ctrl* c : b->ctrls)
+        if (!st) st = c->sync();
+    if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2), "hipMalloc queue");
+    if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2), "queue init");
+    if (!st) st = b->hip(hipMalloc(&b->d_x0s, sizeof(float) * (MPPI_NMAX + 2) * n), "hipMalloc x0s");
+    if (!st) st = b->hip(hipHostMalloc(reinterpret_cast<void**>(&b->h_x0s), sizeof(float) * (MPPI_NMAX + 2) * n, 0),
+                         "hipHostMalloc x0s");
+    if (!st) {
+        std::memset(b->h_x0s, 0, sizeof(float) * (MPPI_NMAX + 2) * n);
+        st = b->build();
+    }
+    if (st) {
+        set_global_error(b->err);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MPPI_OK;
+}
+
+extern "C" void mppi_batch_destroy(mppi_batch_t* b) { delete b; }
+
+extern "C" int mppi_batch_step(mppi_batch_t* b, const float* x0s, float* u0s, int32_t* statuses)
+{
+    if (!b || !x0s || !u0s) return MPPI_E_INVALID;
+    const int n = (int)b->ctrls.size();
+    int st = b->hip(hipSetDevice(b->device), "hipSetDevice");
+    if (st) return st;
+    bool stale = false;
+    for (int c = 0; c < n; ++c) {
+        mppi_ctrl* h = b->ctrls[c];
+        if (h->poisoned) return b->fail(MPPI_E_DEVICE, "controller handle is poisoned");
+        for (int a = 0; a < h->p.n; ++a)
+            if (!std::isfinite(x0s[(size_t)c * MPPI_NMAX + a])) return b->fail(MPPI_E_INVALID, "non-finite x0");
+        if (h->version != b->versions[c]) stale = true;
+    }
+    if (stale) {
+        for (mppi_ctrl* h : b->ctrls)
+            if ((st = h->sync())) return b->fail(st, h->err);
+        if ((st = b->hip(hipStreamSynchronize(b->stream), "sync"))) return st;
+        if ((st = b->build())) return st;
+    }
+    for (int c = 0; c < n; ++c) {
+        float* row = b->h_x0s + (size_t)c * (MPPI_NMAX + 2);
+        std::memset(row, 0, sizeof(float) * (MPPI_NMAX + 2));
+        std::memcpy(row, x0s + (size_t)c * MPPI_NMAX, sizeof(float) * b->ctrls[c]->p.n);
+    }
+    if ((st = b->hip(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"))) return st;
+    if ((st = b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize"))) return st;
+    int first = MPPI_OK;
+    for (int c = 0; c < n; ++c) {
+        const HostResult* r = b->ctrls[c]->h_res;
+        u0s[2 * c] = r->u0[0];
+        u0s[2 * c + 1] = r->u0[1];
+        if (statuses) statuses[c] = r->status;
+        if (r->status != MPPI_OK && first == MPPI_OK) first = r->status;
+    }
+    return first;
+}
+
+extern "C" const char* mppi_batch_last_error(const mppi_batch_t* b) { return b ? b->err.c_str() : global_error(); }

@@ -1,0 +1,722 @@
+// Host runtime of the DBaS-Log-MPPI library: handle lifecycle, configuration
+// checks, device buffers, the single-controller step, inspection, and the
+// batched step (persistent kernel captured in a HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mppi_internal.hpp"
+#include "mppi_runtime.hpp"
+
+using namespace dbas;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+const char* kStatusNames[] = {"MPPI_OK", "MPPI_E_INVALID", "MPPI_E_NOMEM", "MPPI_E_DEVICE", "MPPI_E_NUMERIC",
+                              "MPPI_E_BUSY"};
+
+bool finite_all(const float* v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+int mppi_ctrl::fail(int status, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    if (status == MPPI_E_DEVICE) poisoned = true;
+    return status;
+}
+
+int mppi_ctrl::hip_fail(hipError_t e, const char* what)
+{
+    (void)hipGetLastError();
+    return fail(MPPI_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr)                                         \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return (h)->hip_fail(e_, #expr);   \
+    } while (0)
+
+#define CHECK_HANDLE(h)                                                    \
+    do {                                                                   \
+        if (!(h)) return MPPI_E_INVALID;                                   \
+        if ((h)->poisoned) return MPPI_E_DEVICE;                           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// configuration
+// ---------------------------------------------------------------------------
+extern "C" int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_config* c)
+{
+    if (!c || model < MPPI_QUAD6 || model > MPPI_CAR) return MPPI_E_INVALID;
+    std::memset(c, 0, sizeof *c);
+    c->abi_version = MPPI_ABI_VERSION;
+    c->model = model;
+    c->K = K;
+    c->T = T;
+    c->mass = 0.5f;
+    c->gravity = 9.81f;
+    c->arm = 0.2f;
+    c->inertia = 0.005f;
+    c->wheelbase = 4.0f;
+    c->sigma[0] = c->sigma[1] = 0.5f;
+    c->mu_ln = 0.0f;
+    c->sigma_ln = 0.3f;
+    c->lambda = 1.0f;
+    c->gamma_u = 2.0f;
+    c->gamma_b = 0.5f;
+    c->r_b = 0.1f;
+    c->h_eps = 1e-4f;
+    c->seed = 0;
+    c->normaliser = MPPI_NORM_AUTO;
+    c->init_mode = MPPI_INIT_REPEAT;
+    c->tile_lanes = 0;
+    const int n = state_dim(model);
+    for (int a = 0; a < n; ++a) c->Q[a] = a < 2 ? 1.0f : 0.1f;
+    for (int a = 0; a < n; ++a) c->Qf[a] = 10.0f * c->Q[a];
+    if (model == MPPI_CAR) {
+        c->dt = 0.05f;
+        c->u_min[0] = -1.013f; c->u_max[0] = 1.013f;
+        c->u_min[1] = -2.0f; c->u_max[1] = 2.0f;
+        const float pts[8][2] = {{2, 1.5f}, {2, -1.5f}, {-2, 1.5f}, {-2, -1.5f}, {2, 0}, {-2, 0}, {0, 1.5f}, {0, -1.5f}};
+        c->P = 8;
+        std::memcpy(c->shape, pts, sizeof pts);
+    } else {
+        c->dt = 0.02f;
+        if (model == MPPI_QUAD6) {
+            const float half = 0.5f * c->mass * c->gravity;
+            c->u_min[0] = c->u_min[1] = -half;
+            c->u_max[0] = c->u_max[1] = half;
+        } else {
+            c->u_min[0] = -4.0f; c->u_max[0] = 4.0f;
+            c->u_min[1] = -0.981f; c->u_max[1] = 0.981f;
+            c->sigma[0] = std::sqrt(0.4f);
+            c->sigma[1] = std::sqrt(0.12f);
+        }
+        c->P = 7;
+        for (int i = 0; i < 7; ++i) {
+            c->shape[i][0] = -0.2f + 0.4f * (float)i / 6.0f;
+            c->shape[i][1] = 0.0f;
+        }
+    }
+    return MPPI_OK;
+}
+
+namespace dbas {
+
+std::string validate_config(const mppi_config* c)
+{
+    char b[256];
+    if (!c) return "config is NULL";
+    if (c->abi_version != MPPI_ABI_VERSION) {
+        snprintf(b, sizeof b, "abi_version %u, library has %u", c->abi_version, MPPI_ABI_VERSION);
+        return b;
+    }
+    if (c->model < MPPI_QUAD6 || c->model > MPPI_CAR) return "unknown model";
+    if (c->K < 1 || c->K > MPPI_KMAX) return "K out of range";
+    if (c->T < 1 || c->T > MPPI_TMAX) return "T out of range";
+    if (c->P < 1 || c->P > MPPI_PMAX) return "P out of range";
+    const float scal[] = {c->dt, c->mass, c->gravity, c->arm, c->inertia, c->wheelbase, c->mu_ln, c->sigma_ln,
+                          c->lambda, c->gamma_u, c->gamma_b, c->r_b, c->h_eps};
+    if (!finite_all(scal, sizeof scal / sizeof scal[0])) return "non-finite parameter";
+    if (!finite_all(&c->shape[0][0], 2 * (size_t)c->P)) return "non-finite shape point";
+    if (!finite_all(c->Q, MPPI_NMAX) || !finite_all(c->Qf, MPPI_NMAX)) return "non-finite Q/Qf";
+    if (!(c->dt > 0)) return "dt must be > 0";
+    if (!(c->lambda > 0)) return "lambda must be > 0";
+    if (!(c->gamma_b > 0 && c->gamma_b < 1)) return "gamma_b must lie in (0,1)";
+    if (!(c->h_eps > 0)) return "h_eps must be > 0";
+    if (c->sigma_ln < 0) return "sigma_ln must be >= 0";
+    for (int i = 0; i < MPPI_M; ++i) {
+        if (!std::isfinite(c->sigma[i]) || c->sigma[i] < 0) return "sigma must be finite and >= 0";
+        if (!std::isfinite(c->u_min[i]) || !std::isfinite(c->u_max[i]) || c->u_min[i] > c->u_max[i])
+            return "input limits must be finite with u_min <= u_max";
+    }
+    if (c->model != MPPI_CAR && !(c->mass > 0)) return "mass must be > 0";
+    if (c->model == MPPI_QUAD6 && !(c->inertia > 0)) return "inertia must be > 0";
+    if (c->model == MPPI_CAR && !(c->wheelbase > 0)) return "wheelbase must be > 0";
+    if (c->normaliser < MPPI_NORM_AUTO || c->normaliser > MPPI_NORM_OFF) return "unknown normaliser mode";
+    if (c->init_mode != MPPI_INIT_REPEAT && c->init_mode != MPPI_INIT_ZERO) return "unknown init mode";
+    if (c->tile_lanes != 0 && !tile_lanes_supported(c->tile_lanes)) return "tile_lanes must be 0, 1, 2, 4, 8 or 16";
+    for (int i = 0; i < 7; ++i)
+        if (c->reserved[i] != 0) return "reserved fields must be zero";
+    return "";
+}
+
+}  // namespace dbas
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+mppi_ctrl::~mppi_ctrl()
+{
+    if (device >= 0) (void)hipSetDevice(device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* ptr : allocations) (void)hipFree(ptr);
+    if (d_obs) (void)hipFree(d_obs);
+    if (d_sdf) (void)hipFree(d_sdf);
+    if (h_res) (void)hipHostFree(h_res);
+    for (hipEvent_t e : prof_events)
+        if (e) (void)hipEventDestroy(e);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void* mppi_ctrl::dalloc(size_t bytes, int* status)
+{
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *status = fail(MPPI_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        return nullptr;
+    }
+    allocations.push_back(ptr);
+    return ptr;
+}
+
+int mppi_ctrl::sync()
+{
+    HIP_TRY(this, hipSetDevice(device));
+    HIP_TRY(this, hipStreamSynchronize(stream));
+    return MPPI_OK;
+}
+
+int mppi_ctrl::read_state(CtrlState* out)
+{
+    int s = sync();
+    if (s) return s;
+    HIP_TRY(this, hipMemcpy(out, p.st, sizeof *out, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+int mppi_ctrl::write_state_field(size_t offset, const void* src, size_t bytes)
+{
+    int s = sync();
+    if (s) return s;
+    HIP_TRY(this, hipMemcpy(reinterpret_cast<char*>(p.st) + offset, src, bytes, hipMemcpyHostToDevice));
+    return MPPI_OK;
+}
+
+namespace dbas {
+
+// Lanes per sample: enough groups to give every SIMD of the chip at least a
+// couple of waves, but keep at least a few obstacles per lane.  Used when the
+// configuration leaves tile_lanes at 0 and no measured choice is cached.
+int heuristic_tile_lanes(int K, int J)
+{
+    const long target_lanes = 131072;   // 256 CUs x 4 SIMDs x 2 waves x 64 lanes
+    int G = 1;
+    while (G < 16 && (long)K * G < target_lanes && J / (2 * G) >= 4) G *= 2;
+    return G;
+}
+
+}  // namespace dbas
+
+int mppi_ctrl::configure_tiles(int G)
+{
+    p.G = G;
+    p.spt = kBlock / G;
+    p.tiles = (cfg.K + p.spt - 1) / p.spt;
+    return MPPI_OK;
+}
+
+int mppi_ctrl::alloc_tile_buffers()
+{
+    int st = MPPI_OK;
+    const int T = cfg.T, tiles = p.tiles;
+    p.rho_b = static_cast<double*>(dalloc(sizeof(double) * tiles, &st));
+    p.eta_b = static_cast<double*>(dalloc(sizeof(double) * tiles, &st));
+    p.f_b = static_cast<double*>(dalloc(sizeof(double) * tiles, &st));
+    p.flag_b = static_cast<int32_t*>(dalloc(sizeof(int32_t) * tiles, &st));
+    p.partN = static_cast<double*>(dalloc(sizeof(double) * (size_t)2 * T * tiles, &st));
+    if (st) return st;
+    HIP_TRY(this, hipMemset(p.f_b, 0, sizeof(double) * tiles));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_t** out)
+{
+    if (!out) return MPPI_E_INVALID;
+    *out = nullptr;
+    std::string why = validate_config(cfg);
+    if (!why.empty()) {
+        set_global_error("mppi_create: " + why);
+        return MPPI_E_INVALID;
+    }
+    mppi_ctrl* h = new (std::nothrow) mppi_ctrl();
+    if (!h) return MPPI_E_NOMEM;
+    h->cfg = *cfg;
+    h->device = dev ? dev->device : 0;
+    int st = MPPI_OK;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) {
+        set_global_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+        delete h;
+        return MPPI_E_DEVICE;
+    }
+    if (dev && dev->stream) {
+        h->stream = static_cast<hipStream_t>(dev->stream);
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            set_global_error(std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            delete h;
+            return MPPI_E_DEVICE;
+        }
+        h->own_stream = true;
+    }
+
+    DevParams& p = h->p;
+    std::memset(&p, 0, sizeof p);
+    const int K = cfg->K, T = cfg->T, n = state_dim(cfg->model);
+    p.model = cfg->model;
+    p.K = K;
+    p.Kp = round_up(K, 64);
+    p.T = T;
+    p.P = cfg->P;
+    p.J = 0;
+    p.n = n;
+    p.normaliser = cfg->normaliser;
+    p.init_mode = cfg->init_mode;
+    p.dt = cfg->dt;
+    p.mass = cfg->mass;
+    p.gravity = cfg->gravity;
+    p.arm = cfg->arm;
+    p.inertia = cfg->inertia;
+    p.wheelbase = cfg->wheelbase;
+    for (int i = 0; i < kM; ++i) {
+        p.u_min[i] = cfg->u_min[i];
+        p.u_max[i] = cfg->u_max[i];
+        p.sigma[i] = cfg->sigma[i];
+    }
+    p.mu_ln = cfg->mu_ln;
+    p.sigma_ln = cfg->sigma_ln;
+    p.lambda = cfg->lambda;
+    p.gamma_u = cfg->gamma_u;
+    p.gamma_b = cfg->gamma_b;
+    p.r_b = cfg->r_b;
+    p.h_eps = cfg->h_eps;
+    for (int a = 0; a < MPPI_NMAX; ++a) {
+        p.Q[a] = a < n ? cfg->Q[a] : 0.0f;
+        p.Qf[a] = a < n ? cfg->Qf[a] : 0.0f;
+    }
+    std::memcpy(p.shape, cfg->shape, sizeof p.shape);
+    p.seed_lo = (uint32_t)cfg->seed;
+    p.seed_hi = (uint32_t)(cfg->seed >> 32);
+
+    h->configure_tiles(cfg->tile_lanes ? cfg->tile_lanes : heuristic_tile_lanes(K, 0));
+    h->tiles_fixed = cfg->tile_lanes != 0;
+
+    p.U = static_cast<float*>(h->dalloc(sizeof(float) * 2 * T * kM, &st));
+    p.Ustar = static_cast<float*>(h->dalloc(sizeof(float) * T * kM, &st));
+    p.du = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)T * kM * p.Kp, &st));
+    p.S = static_cast<float*>(h->dalloc(sizeof(float) * 2 * (size_t)p.Kp, &st));
+    p.e = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)p.Kp, &st));
+    p.xref = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)(T + 1) * n, &st));
+    p.st = static_cast<CtrlState*>(h->dalloc(sizeof(CtrlState), &st));
+    if (st) {
+        set_global_error(h->err);
+        delete h;
+        return st;
+    }
+    if (!st) st = h->alloc_tile_buffers();
+    if (st) {
+        set_global_error(h->err);
+        delete h;
+        return st;
+    }
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->h_res), sizeof(HostResult), hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p.res), h->h_res, 0);
+    if (e != hipSuccess) {
+        set_global_error(std::string("pinned result buffer: ") + hipGetErrorString(e));
+        delete h;
+        return MPPI_E_NOMEM;
+    }
+    std::memset(h->h_res, 0, sizeof(HostResult));
+
+    CtrlState s0;
+    std::memset(&s0, 0, sizeof s0);
+    s0.S_e = 1.0f;
+    e = hipMemset(p.U, 0, sizeof(float) * 2 * T * kM);
+    if (e == hipSuccess) e = hipMemset(p.Ustar, 0, sizeof(float) * T * kM);
+    if (e == hipSuccess) e = hipMemset(p.du, 0, sizeof(float) * (size_t)T * kM * p.Kp);
+    if (e == hipSuccess) e = hipMemset(p.S, 0, sizeof(float) * 2 * (size_t)p.Kp);
+    if (e == hipSuccess) e = hipMemset(p.e, 0, sizeof(float) * (size_t)p.Kp);
+    if (e == hipSuccess) e = hipMemset(const_cast<float*>(p.xref), 0, sizeof(float) * (size_t)(T + 1) * n);
+    if (e == hipSuccess) e = hipMemcpy(p.st, &s0, sizeof s0, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        set_global_error(std::string("initialising buffers: ") + hipGetErrorString(e));
+        delete h;
+        return MPPI_E_DEVICE;
+    }
+    *out = h;
+    return MPPI_OK;
+}
+
+extern "C" void mppi_destroy(mppi_t* h) { delete h; }
+
+// The tile shape depends on (model, K, T, J, P); re-choose it when J changes
+// and the configuration did not fix it.
+int mppi_ctrl::retile()
+{
+    if (tiles_fixed) return MPPI_OK;
+    const int G = choose_tile_lanes(this);
+    if (G == p.G) return MPPI_OK;
+    int s = sync();
+    if (s) return s;
+    for (double* ptr : {p.rho_b, p.eta_b, p.f_b}) {
+        allocations.erase(std::find(allocations.begin(), allocations.end(), (void*)ptr));
+        (void)hipFree(ptr);
+    }
+    allocations.erase(std::find(allocations.begin(), allocations.end(), (void*)p.flag_b));
+    (void)hipFree(p.flag_b);
+    allocations.erase(std::find(allocations.begin(), allocations.end(), (void*)p.partN));
+    (void)hipFree(p.partN);
+    configure_tiles(G);
+    ++version;
+    return alloc_tile_buffers();
+}
+
+extern "C" int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int32_t mem)
+{
+    CHECK_HANDLE(h);
+    if (J < 0 || J > MPPI_JMAX) return h->fail(MPPI_E_INVALID, "J=%d outside 0..%d", J, MPPI_JMAX);
+    if (J > 0 && !cxcyr) return h->fail(MPPI_E_INVALID, "obstacles pointer is NULL");
+    std::vector<float> tmp;
+    if (J > 0 && mem == MPPI_MEM_HOST) {
+        if (!finite_all(cxcyr, (size_t)3 * J)) return h->fail(MPPI_E_INVALID, "non-finite obstacle");
+        for (int j = 0; j < J; ++j)
+            if (cxcyr[3 * j + 2] < 0) return h->fail(MPPI_E_INVALID, "negative obstacle radius");
+    }
+    int s = h->sync();
+    if (s) return s;
+    if (J > h->obs_cap) {
+        if (h->d_obs) (void)hipFree(h->d_obs);
+        h->d_obs = nullptr;
+        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&h->d_obs), sizeof(float) * 3 * (size_t)J));
+        h->obs_cap = J;
+    }
+    if (J > 0) {
+        HIP_TRY(h, hipMemcpy(h->d_obs, cxcyr, sizeof(float) * 3 * (size_t)J,
+                             mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    }
+    h->p.obs = h->d_obs;
+    h->p.J = J;
+    ++h->version;
+    return h->retile();
+}
+
+extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float y0, float res, const float* sdf,
+                                int32_t mem)
+{
+    CHECK_HANDLE(h);
+    if (!sdf) {
+        h->p.sdf = nullptr;
+        h->p.map_w = h->p.map_h = 0;
+        ++h->version;
+        return MPPI_OK;
+    }
+    if (W < 2 || H < 2 || (long)W * H > (1L << 26)) return h->fail(MPPI_E_INVALID, "costmap must be at least 2x2");
+    if (!(res > 0) || !std::isfinite(res) || !std::isfinite(x0) || !std::isfinite(y0))
+        return h->fail(MPPI_E_INVALID, "costmap origin/resolution invalid");
+    if (mem == MPPI_MEM_HOST && !finite_all(sdf, (size_t)W * H)) return h->fail(MPPI_E_INVALID, "non-finite costmap");
+    int s = h->sync();
+    if (s) return s;
+    const size_t bytes = sizeof(float) * (size_t)W * H;
+    if (bytes > h->sdf_bytes) {
+        if (h->d_sdf) (void)hipFree(h->d_sdf);
+        h->d_sdf = nullptr;
+        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&h->d_sdf), bytes));
+        h->sdf_bytes = bytes;
+    }
+    HIP_TRY(h, hipMemcpy(h->d_sdf, sdf, bytes, mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    h->p.sdf = h->d_sdf;
+    h->p.map_w = W;
+    h->p.map_h = H;
+    h->p.map_x0 = x0;
+    h->p.map_y0 = y0;
+    h->p.map_res = res;
+    ++h->version;
+    return MPPI_OK;
+}
+
+extern "C" int mppi_set_reference(mppi_t* h, const float* x_ref, int32_t mem)
+{
+    CHECK_HANDLE(h);
+    if (!x_ref) return h->fail(MPPI_E_INVALID, "x_ref is NULL");
+    const size_t cnt = (size_t)(h->cfg.T + 1) * h->p.n;
+    if (mem == MPPI_MEM_HOST && !finite_all(x_ref, cnt)) return h->fail(MPPI_E_INVALID, "non-finite reference");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipMemcpyAsync(const_cast<float*>(h->p.xref), x_ref, sizeof(float) * cnt,
+                              mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    if (mem == MPPI_MEM_HOST) HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_set_exploration(mppi_t* h, float S_e)
+{
+    CHECK_HANDLE(h);
+    if (!(S_e > 0) || !std::isfinite(S_e)) return h->fail(MPPI_E_INVALID, "S_e must be finite and > 0");
+    return h->write_state_field(offsetof(CtrlState, S_e), &S_e, sizeof S_e);
+}
+
+extern "C" int mppi_set_controls(mppi_t* h, const float* U, int32_t mem)
+{
+    CHECK_HANDLE(h);
+    if (!U) return h->fail(MPPI_E_INVALID, "U is NULL");
+    const size_t cnt = (size_t)h->cfg.T * kM;
+    if (mem == MPPI_MEM_HOST && !finite_all(U, cnt)) return h->fail(MPPI_E_INVALID, "non-finite controls");
+    CtrlState st;
+    int s = h->read_state(&st);
+    if (s) return s;
+    HIP_TRY(h, hipMemcpy(h->p.U + (size_t)(st.iter & 1u) * cnt, U, sizeof(float) * cnt,
+                         mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    return MPPI_OK;
+}
+
+int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_dev)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (x0_host) std::memcpy(a.x0, x0_host, sizeof(float) * p.n);
+    a.x0_ptr = x0_dev;
+    a.u0_dev = u0_dev;
+    HIP_TRY(this, hipSetDevice(device));
+    hipEvent_t* ev = nullptr;
+    if (profiling) {
+        if (prof_used * 3 < (int)prof_events.size()) ev = &prof_events[(size_t)prof_used++ * 3];
+        else ++prof_dropped;
+    }
+    if (ev) HIP_TRY(this, hipEventRecord(ev[0], stream));
+    HIP_TRY(this, launch_rollout(p, a, stream));
+    if (ev) HIP_TRY(this, hipEventRecord(ev[1], stream));
+    HIP_TRY(this, launch_update(p, a, stream));
+    if (ev) HIP_TRY(this, hipEventRecord(ev[2], stream));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_profile_enable(mppi_t* h, int32_t on)
+{
+    CHECK_HANDLE(h);
+    if (on && h->prof_events.empty()) {
+        HIP_TRY(h, hipSetDevice(h->device));
+        h->prof_events.resize(3 * 4096, nullptr);
+        for (auto& e : h->prof_events) HIP_TRY(h, hipEventCreate(&e));
+    }
+    h->profiling = on != 0;
+    h->prof_used = 0;
+    h->prof_dropped = 0;
+    return MPPI_OK;
+}
+
+extern "C" int mppi_profile_read(mppi_t* h, mppi_profile* out)
+{
+    CHECK_HANDLE(h);
+    if (!out) return MPPI_E_INVALID;
+    int s = h->sync();
+    if (s) return s;
+    out->iterations = h->prof_used;
+    out->dropped = h->prof_dropped;
+    out->rollout_ms = out->update_ms = 0.0;
+    for (int i = 0; i < h->prof_used; ++i) {
+        float a = 0.0f, b = 0.0f;
+        HIP_TRY(h, hipEventElapsedTime(&a, h->prof_events[3 * i], h->prof_events[3 * i + 1]));
+        HIP_TRY(h, hipEventElapsedTime(&b, h->prof_events[3 * i + 1], h->prof_events[3 * i + 2]));
+        out->rollout_ms += a;
+        out->update_ms += b;
+    }
+    h->prof_used = 0;
+    h->prof_dropped = 0;
+    return MPPI_OK;
+}
+
+extern "C" int mppi_step(mppi_t* h, const float* x0, float* u0)
+{
+    CHECK_HANDLE(h);
+    if (!x0 || !u0) return h->fail(MPPI_E_INVALID, "x0/u0 is NULL");
+    if (!finite_all(x0, h->p.n)) return h->fail(MPPI_E_INVALID, "non-finite x0");
+    int s = h->launch_step(x0, nullptr, nullptr);
+    if (s) return s;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const HostResult* r = h->h_res;
+    u0[0] = r->u0[0];
+    u0[1] = r->u0[1];
+    if (r->status != MPPI_OK) return h->fail(r->status, "iteration status %d (%s)", r->status, mppi_status_string(r->status));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_step_async(mppi_t* h, const float* x0_device, float* u0_device)
+{
+    CHECK_HANDLE(h);
+    if (!x0_device) return h->fail(MPPI_E_INVALID, "x0_device is NULL");
+    return h->launch_step(nullptr, x0_device, u0_device);
+}
+
+extern "C" int mppi_synchronize(mppi_t* h)
+{
+    CHECK_HANDLE(h);
+    int s = h->sync();
+    if (s) return s;
+    CtrlState st;
+    HIP_TRY(h, hipMemcpy(&st, h->p.st, sizeof st, hipMemcpyDeviceToHost));
+    return st.iter == 0 ? MPPI_OK : st.status;
+}
+
+extern "C" int mppi_get_controls(mppi_t* h, float* U)
+{
+    CHECK_HANDLE(h);
+    if (!U) return MPPI_E_INVALID;
+    CtrlState st;
+    int s = h->read_state(&st);
+    if (s) return s;
+    const size_t cnt = (size_t)h->cfg.T * kM;
+    HIP_TRY(h, hipMemcpy(U, h->p.U + (size_t)(st.iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_last_optimal(mppi_t* h, float* Ustar)
+{
+    CHECK_HANDLE(h);
+    if (!Ustar) return MPPI_E_INVALID;
+    int s = h->sync();
+    if (s) return s;
+    HIP_TRY(h, hipMemcpy(Ustar, h->p.Ustar, sizeof(float) * h->cfg.T * kM, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_costs(mppi_t* h, double* S)
+{
+    CHECK_HANDLE(h);
+    if (!S) return MPPI_E_INVALID;
+    int s = h->sync();
+    if (s) return s;
+    std::vector<float> buf(2 * (size_t)h->p.Kp);
+    CtrlState st;
+    HIP_TRY(h, hipMemcpy(&st, h->p.st, sizeof st, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(buf.data(), h->p.S, sizeof(float) * buf.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < h->cfg.K; ++k) S[k] = ((double)buf[k] + (double)buf[h->p.Kp + k]) + st.cshift;
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_weights(mppi_t* h, double* w)
+{
+    CHECK_HANDLE(h);
+    if (!w) return MPPI_E_INVALID;
+    double* d_w = nullptr;
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&d_w), sizeof(double) * h->cfg.K));
+    hipError_t e = launch_weights(h->p, d_w, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(w, d_w, sizeof(double) * h->cfg.K, hipMemcpyDeviceToHost);
+    (void)hipFree(d_w);
+    if (e != hipSuccess) return h->hip_fail(e, "mppi_get_weights");
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_noise(mppi_t* h, float* du)
+{
+    CHECK_HANDLE(h);
+    if (!du) return MPPI_E_INVALID;
+    int s = h->sync();
+    if (s) return s;
+    const int K = h->cfg.K, T = h->cfg.T, Kp = h->p.Kp;
+    std::vector<float> buf((size_t)T * kM * Kp);
+    HIP_TRY(h, hipMemcpy(buf.data(), h->p.du, sizeof(float) * buf.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < K; ++k)
+        for (int t = 0; t < T; ++t)
+            for (int c = 0; c < kM; ++c) du[((size_t)k * T + t) * kM + c] = buf[(size_t)(t * kM + c) * Kp + k];
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
+{
+    CHECK_HANDLE(h);
+    if (!info) return MPPI_E_INVALID;
+    CtrlState st;
+    int s = h->read_state(&st);
+    if (s) return s;
+    info->counter = st.last_counter;
+    info->status = st.iter == 0 ? MPPI_OK : st.status;
+    info->fp64_tiles = st.fp64_tiles;
+    info->rho = st.rho;
+    info->eta = st.eta;
+    info->beta0 = st.beta0;
+    info->beta_d = st.beta_d;
+    info->tile_lanes = h->p.G;
+    info->tiles = h->p.tiles;
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_philox_words(mppi_t* h, uint64_t counter, uint32_t* words)
+{
+    CHECK_HANDLE(h);
+    if (!words) return MPPI_E_INVALID;
+    const size_t n = (size_t)h->cfg.K * h->cfg.T * 4;
+    uint32_t* d = nullptr;
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&d), sizeof(uint32_t) * n));
+    hipError_t e = launch_philox_words(h->p, counter, d, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(words, d, sizeof(uint32_t) * n, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return h->hip_fail(e, "mppi_get_philox_words");
+    return MPPI_OK;
+}
+
+extern "C" int mppi_get_state(mppi_t* h, mppi_state* out)
+{
+    CHECK_HANDLE(h);
+    if (!out || !out->U || out->T != h->cfg.T) return h->fail(MPPI_E_INVALID, "state buffer must have T=%d", h->cfg.T);
+    CtrlState st;
+    int s = h->read_state(&st);
+    if (s) return s;
+    out->counter = st.counter;
+    out->S_e = st.S_e;
+    const size_t cnt = (size_t)h->cfg.T * kM;
+    HIP_TRY(h, hipMemcpy(out->U, h->p.U + (size_t)(st.iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+extern "C" int mppi_set_state(mppi_t* h, const mppi_state* in)
+{
+    CHECK_HANDLE(h);
+    if (!in || !in->U || in->T != h->cfg.T) return h->fail(MPPI_E_INVALID, "state buffer must have T=%d", h->cfg.T);
+    if (!(in->S_e > 0) || !std::isfinite(in->S_e)) return h->fail(MPPI_E_INVALID, "S_e must be finite and > 0");
+    int s = mppi_set_controls(h, in->U, MPPI_MEM_HOST);
+    if (s) return s;
+    s = h->write_state_field(offsetof(CtrlState, counter), &in->counter, sizeof in->counter);
+    if (s) return s;
+    return h->write_state_field(offsetof(CtrlState, S_e), &in->S_e, sizeof in->S_e);
+}
+
+extern "C" const char* mppi_last_error(const mppi_t* h) { return h ? h->err.c_str() : global_error(); }
+
+extern "C" const char* mppi_status_string(int32_t s)
+{
+    return (s >= 0 && s <= 5) ? kStatusNames[s] : "MPPI_E_UNKNOWN";
+}
+
+extern "C" void* mppi_stream(const mppi_t* h) { return h ? (void*)h->stream : nullptr; }

@@ -1,0 +1,54 @@
+// Host-side handle of one controller (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "mppi_internal.hpp"
+
+struct mppi_ctrl {
+    mppi_config cfg{};
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    bool tiles_fixed = false;
+    uint64_t version = 0;            // bumps whenever DevParams change (batches re-upload)
+    std::string err;
+    dbas::DevParams p{};
+    std::vector<void*> allocations;
+    float* d_obs = nullptr;
+    int obs_cap = 0;
+    float* d_sdf = nullptr;
+    size_t sdf_bytes = 0;
+    dbas::HostResult* h_res = nullptr;
+    // kernel timing (mppi_profile_*): event triples per recorded iteration
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_events;   // 3 per slot
+    int prof_used = 0;
+    int64_t prof_dropped = 0;
+
+    ~mppi_ctrl();
+    int fail(int status, const char* fmt, ...);
+    int hip_fail(hipError_t e, const char* what);
+    void* dalloc(size_t bytes, int* status);
+    int sync();
+    int read_state(dbas::CtrlState* out);
+    int write_state_field(size_t offset, const void* src, size_t bytes);
+    int configure_tiles(int G);
+    int alloc_tile_buffers();
+    int retile();
+    int launch_step(const float* x0_host, const float* x0_dev, float* u0_dev);
+};
+
+namespace dbas {
+std::string validate_config(const mppi_config* c);
+int heuristic_tile_lanes(int K, int J);
+// Autotuned lanes-per-sample for this controller's (model, K, T, J, P).
+int choose_tile_lanes(mppi_ctrl* h);
+}  // namespace dbas
+
+void set_global_error(const std::string& s);
+const char* global_error();

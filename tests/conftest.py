@@ -18,3 +18,17 @@ def orc():
     if not os.path.exists(oracle.LIB_PATH):
         oracle.build()
     return oracle
+
+
+def f32_params(params: dict) -> dict:
+    """The parameter dict with every real rounded to binary32, i.e. exactly
+    the values the GPU library receives, so the oracle sees the same inputs."""
+    import numpy as np
+
+    def r(v):
+        if isinstance(v, float):
+            return float(np.float32(v))
+        if isinstance(v, (list, tuple)):
+            return [r(x) for x in v]
+        return v
+    return {k: r(v) for k, v in params.items()}

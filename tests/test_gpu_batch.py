@@ -1,0 +1,82 @@
+"""Batched persistent launch: each controller's result is the same alone and
+in the mixed batch (bit-exact: a controller's tile shape depends only on its
+own shape), and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import f32_params
+from paper_2504_06437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(n=10, seed=21):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wls = []
+    for i in range(n):
+        wl = W.mixed_controller(rng, 100 + i, K=int(round(2 ** rng.uniform(6, 10))), T=int(rng.integers(5, 30)),
+                                J=int(rng.integers(0, 60)))
+        wl["U0"] = W.random_controls(rng, wl["params"]["T"], 0.2)
+        wls.append(wl)
+    return wls
+
+
+def _make(wl):
+    from paper_2504_06437_amd.controller import Controller
+    c = Controller(wl["params"])
+    c.load_workload(wl)
+    return c
+
+
+def test_batch_equals_alone_and_oracle():
+    from paper_2504_06437_amd.controller import Batch
+    wls = _mix()
+    alone = [_make(wl) for wl in wls]
+    mixed = [_make(wl) for wl in wls]
+    batch = Batch(mixed)
+    for step in range(3):
+        states = [c.get_state() for c in mixed]
+        x0s = [wl["x0"] for wl in wls]
+        u_b, sts = batch.step(x0s)
+        assert np.all(sts == 0)
+        for i, (a, m, wl) in enumerate(zip(alone, mixed, wls)):
+            u_a = a.step(wl["x0"])
+            np.testing.assert_array_equal(u_a, u_b[i])
+            np.testing.assert_array_equal(a.controls(), m.controls())
+            np.testing.assert_array_equal(a.costs(), m.costs())
+            if step == 0:
+                p = f32_params(wl["params"])
+                ref = oracle.step(p, oracle.World.from_workload(wl), wl["x0"], states[i]["U"], wl["x_ref"], 1.0,
+                                  states[i]["counter"])
+                S = m.costs()
+                # cost bound of test_gpu_parity: relative 1e-4 plus the barrier's conditioning
+                bound = 1e-4 * np.maximum(np.abs(ref["S"]), 1.0) + 1e-5 * ref["sens"]
+                assert np.all(np.abs(S - ref["S"]) <= bound)
+                scale = np.asarray(p["sigma"])
+                assert np.all(np.abs(m.last_optimal() - ref["Ustar"]) <= 1e-4 * (np.abs(ref["Ustar"]) + scale))
+    batch.close()
+    for c in alone + mixed:
+        c.close()
+
+
+def test_batch_replays_follow_obstacle_changes():
+    """Changing a controller's obstacles between graph replays rebuilds the
+    batch; results still equal the standalone controller's."""
+    from paper_2504_06437_amd.controller import Batch
+    wls = _mix(4, seed=5)
+    alone = [_make(wl) for wl in wls]
+    mixed = [_make(wl) for wl in wls]
+    batch = Batch(mixed)
+    batch.step([wl["x0"] for wl in wls])
+    for a, wl in zip(alone, wls):
+        a.step(wl["x0"])
+    new_obs = np.array([[1.0, 1.5, 0.3], [2.0, 2.5, 0.4], [3.0, 1.0, 0.5]], dtype=np.float32)
+    alone[1].set_obstacles(new_obs)
+    mixed[1].set_obstacles(new_obs)
+    u_b, _ = batch.step([wl["x0"] for wl in wls])
+    for i, (a, wl) in enumerate(zip(alone, wls)):
+        np.testing.assert_array_equal(a.step(wl["x0"]), u_b[i])
+    batch.close()
+    for c in alone + mixed:
+        c.close()

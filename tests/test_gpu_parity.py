@@ -1,0 +1,334 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (stated once, used everywhere below):
+  * Philox words: bit-exact.
+  * noise du: |d| <= 1e-5 |ref| + 1e-6 sqrt(S_e) sigma_c  (FP32 log/sqrt/sincospi/exp
+    of exactly equal uniforms: a few ulp).
+  * costs S_k: |d| <= 1e-4 max(|S_ref|, 1) + DP * sens_k.  sens_k (from the
+    oracle) bounds |dS_k| per metre of shape-point displacement through the
+    barrier: R_B/(1-gamma_B) sum_t sum_pairs |dB/dp|, which grows like 1/h^2
+    near a boundary.  DP = 1e-5 m is the FP32 position-error budget (positions
+    of <= 10 m in the iteration's local frame, ulp ~1e-6 m, over <= 100 Euler
+    steps).  Far from obstacles the first term governs: the test requires it
+    to govern for most samples.
+  * weights: normwise |dw| <= 1e-4 max w_ref; elementwise relative 1e-4 plus
+    the propagated cost error expm1(2 max|dS| / lambda) over the weighted
+    samples; the GPU softmax alone (GPU costs through the FP64 softmax) 1e-5.
+  * U*, shifted U, u0: |d| <= 1e-4 (|ref| + sqrt(S_e) sigma_c).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import f32_params
+from paper_2504_06437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_S = 1e-4
+TOL_W = 1e-4
+TOL_U = 1e-4
+DP = 1e-5
+
+
+def _check_costs(Sg, Sr, sens, what=""):
+    base = TOL_S * np.maximum(np.abs(Sr), 1.0)
+    cond = DP * sens
+    assert np.mean(cond <= base) >= 0.5, f"{what}: the relative bound governs only {np.mean(cond <= base):.2f}"
+    d = np.abs(Sg - Sr)
+    assert np.all(np.isfinite(Sg))
+    assert np.all(d <= base + cond), f"{what} costs {np.max(d / (base + cond))} of the bound"
+
+
+def _ctrl(wl, **over):
+    from paper_2504_06437_amd.controller import Controller
+    p = dict(wl["params"])
+    p.update(over)
+    c = Controller(p)
+    c.load_workload(wl)
+    return c, p
+
+
+def _world(wl):
+    return oracle.World.from_workload(wl)
+
+
+def _check_weights(wg, wr, Sg, Sr, lam, what=""):
+    """Weights: normwise relative 1e-4; elementwise relative 1e-4 plus what
+    the cost difference itself propagates (w_k ~ exp(-S_k/lambda), so
+    |dw_k|/w_k <= expm1(2 max|dS|/lambda) to first order); and the GPU's
+    softmax alone (its own costs through the FP64 softmax) to 1e-5."""
+    assert np.max(np.abs(wg - wr)) <= TOL_W * wr.max(), f"{what} weights normwise"
+    big = wr >= 1e-8 * wr.max()
+    dS = np.max(np.abs(Sg - Sr)[big])
+    bound = TOL_W + np.expm1(2.0 * dS / lam)
+    rel = np.abs(wg[big] - wr[big]) / wr[big]
+    assert rel.max() <= bound, f"{what} weights {rel.max()} > {bound}"
+    assert np.all(np.abs(wg[~big] - wr[~big]) <= 1e-8 * wr.max()), f"{what} small weights"
+    _, w_iso, _, _ = oracle.weights(Sg, lam)
+    big = w_iso >= 1e-8 * w_iso.max()
+    assert np.max(np.abs(wg[big] - w_iso[big]) / w_iso[big]) <= 1e-5, f"{what} softmax in isolation"
+
+
+def _check(gpu: dict, ref: dict, p: dict, S_e=1.0, what=""):
+    scale = math.sqrt(S_e) * np.asarray(p["sigma"], dtype=np.float64)
+    if "du" in gpu:
+        d = np.abs(gpu["du"] - ref["du"])
+        assert np.all(d <= 1e-5 * np.abs(ref["du"]) + 1e-6 * scale + 1e-30), f"{what} noise {d.max()}"
+    _check_costs(gpu["S"], ref["S"], ref["sens"], what)
+    _check_weights(gpu["w"], ref["w"], gpu["S"], ref["S"], p["lambda"], what)
+    for key in ("Ustar", "Unext"):
+        d = np.abs(gpu[key] - ref[key])
+        assert np.all(d <= TOL_U * (np.abs(ref[key]) + scale)), f"{what} {key} {d.max()}"
+    d = np.abs(gpu["u0"] - ref["u0"])
+    assert np.all(d <= TOL_U * (np.abs(ref["u0"]) + scale)), f"{what} u0"
+
+
+def _gpu_outputs(c, u0):
+    return {"S": c.costs(), "w": c.weights(), "du": c.noise().astype(np.float64),
+            "Ustar": c.last_optimal().astype(np.float64), "Unext": c.controls().astype(np.float64),
+            "u0": np.asarray(u0, dtype=np.float64)}
+
+
+def _one_iteration(wl, S_e=1.0, **over):
+    c, p = _ctrl(wl, **over)
+    if S_e != 1.0:
+        c.set_exploration(S_e)
+    st = c.get_state()
+    u0 = c.step(wl["x0"])
+    g = _gpu_outputs(c, u0)
+    info = c.info()
+    ref = oracle.step(f32_params(p), _world(wl), wl["x0"], st["U"], wl["x_ref"], np.float32(S_e), st["counter"])
+    assert ref["status"] == 0 and info["status"] == 0
+    _check(g, ref, p, S_e, what=str(over))
+    c.close()
+    return g, ref, info
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("counter", [0, 1, 2**32 + 5, 2**63 + 7])
+def test_philox_words_bit_exact(counter):
+    wl = W.quad_small(K=300, T=7)
+    c, p = _ctrl(wl, seed=0x0123456789ABCDEF)
+    g = c.philox_words(counter)
+    want = oracle.noise_words(f32_params(p), counter)
+    assert np.array_equal(g, want)
+    c.close()
+
+
+@pytest.mark.parametrize("name,make", [
+    ("tiny_quad6", lambda: W.tiny("quad6")),
+    ("tiny_quad5", lambda: W.tiny("quad5")),
+    ("tiny_car", lambda: W.tiny("car")),
+    ("quad_small", lambda: W.quad_small()),
+    ("quad_small_ragged", lambda: W.quad_small(K=300, T=7)),
+    ("car_medium", lambda: W.car(K=1000, T=20, J=40)),
+    ("quad5_medium", lambda: W.quad_small(K=777, T=15, J=25, model="quad5")),
+    ("quad_costmap", lambda: W.quad_large(K=2048, T=30, J=100, cells=128)),
+])
+def test_iteration_matches_oracle(name, make):
+    _one_iteration(make())
+
+
+@pytest.mark.parametrize("G", [1, 2, 4, 8, 16])
+def test_every_tile_shape_matches_oracle(G):
+    _one_iteration(W.quad_small(K=300, T=11, J=13), tile_lanes=G)
+    _one_iteration(W.car(K=200, T=9, J=21), tile_lanes=G)
+
+
+def test_exploration_rate_scales_noise_and_control_cost():
+    wl = W.quad_small(K=512, T=20)
+    rng = np.random.Generator(np.random.PCG64(3))
+    wl["U0"] = W.random_controls(rng, 20)
+    _one_iteration(wl, S_e=2.75)
+
+
+def test_no_obstacles_and_fp64_normaliser_modes():
+    wl = W.quad_small(K=256, T=20, J=10)
+    wl["obstacles"] = np.zeros((0, 3), dtype=np.float32)
+    _one_iteration(wl, normaliser="on")
+    _one_iteration(W.quad_small(K=256, T=20), normaliser="off")
+
+
+def test_receding_horizon_teacher_forced():
+    """Several control steps; each GPU iteration is compared with the oracle
+    started from the GPU's own warm start, counter and state."""
+    wl = W.quad_small(K=512, T=20)
+    c, p = _ctrl(wl)
+    pf = f32_params(p)
+    x = wl["x0"].astype(np.float32)
+    for step in range(6):
+        xr = W.reference(wl, x)
+        c.set_reference(xr)
+        st = c.get_state()
+        u0 = c.step(x)
+        g = _gpu_outputs(c, u0)
+        wl2 = dict(wl, x_ref=xr)
+        ref = oracle.step(pf, _world(wl2), x, st["U"], xr, 1.0, st["counter"])
+        assert st["counter"] == step
+        _check(g, ref, p, what=f"step {step}")
+        x = oracle.dynamics(pf, x, u0).astype(np.float32)   # the simulated plant
+    c.close()
+
+
+def test_full_size_vehicle_workload():
+    """Ground vehicle, K=4096, T=50, 100 obstacles: every output compared."""
+    _, _, info = _one_iteration(W.car())
+    assert info["tiles"] >= 1
+
+
+def test_full_size_quadrotor_with_costmap_sampled():
+    """Quadrotor, K=16384, T=100, 400 obstacles + 512x512 costmap, FP64
+    normaliser: Philox words of sampled (k, t), the costs of 64 sampled
+    samples by the oracle's rollout, and the weights and update given the
+    GPU's own costs and noise through the oracle's softmax and update."""
+    wl = W.quad_large()
+    c, p = _ctrl(wl)
+    pf = f32_params(p)
+    st = c.get_state()
+    u0 = c.step(wl["x0"])
+    info = c.info()
+    assert info["status"] == 0 and info["fp64_tiles"] == info["tiles"]
+    S, w, du, Us = c.costs(), c.weights(), c.noise().astype(np.float64), c.last_optimal().astype(np.float64)
+    words = c.philox_words(st["counter"])
+    rng = np.random.Generator(np.random.PCG64(11))
+    ks = np.sort(rng.choice(p["K"], size=64, replace=False))
+    for k in ks[:8]:
+        for t in (0, 57, 99):
+            want = oracle.philox([k, t, st["counter"] & 0xFFFFFFFF, st["counter"] >> 32],
+                                 [p["seed"] & 0xFFFFFFFF, p["seed"] >> 32])
+            assert list(words[k, t]) == want
+    world = _world(wl)
+    du_ref = oracle.noise(dict(pf, K=p["K"]), st["counter"])
+    beta_d = oracle.fused_barrier(pf, world, wl["x_ref"][-1])
+    S_ref, sens = np.zeros(len(ks)), np.zeros(len(ks))
+    for i, k in enumerate(ks):
+        S_ref[i], _, _, _, sens[i] = oracle.rollout_one(pf, world, wl["x0"], st["U"], du_ref[k], wl["x_ref"], 1.0,
+                                                        beta_d, with_clearance=True)
+    _check_costs(S[ks], S_ref, sens, "sampled costs")
+    np.testing.assert_allclose(du[ks], du_ref[ks], rtol=1e-5, atol=1e-6 * 0.5)
+    st_w, w_ref, _, _ = oracle.weights(S, p["lambda"])
+    big = w_ref >= 1e-8 * w_ref.max()
+    assert np.max(np.abs(w[big] - w_ref[big]) / w_ref[big]) <= 1e-5
+    Us_ref = oracle.update(st["U"], du, w)
+    assert np.all(np.abs(Us - Us_ref) <= TOL_U * (np.abs(Us_ref) + 0.5))
+    assert abs(w.sum() - 1.0) < 1e-9
+    np.testing.assert_allclose(u0, Us[0], rtol=0, atol=0)
+    c.close()
+
+
+# --- special cases the paper fixes -------------------------------------------
+
+def test_zero_noise_keeps_the_sequence():
+    wl = W.quad_small(K=256, T=20)
+    rng = np.random.Generator(np.random.PCG64(4))
+    wl["U0"] = W.random_controls(rng, 20)
+    c, p = _ctrl(wl, sigma=[0.0, 0.0])
+    u0 = c.step(wl["x0"])
+    du, S, w, Us, U = c.noise(), c.costs(), c.weights(), c.last_optimal(), c.controls()
+    assert np.all(du == 0.0)
+    assert np.all(S == S[0])
+    np.testing.assert_allclose(w, 1.0 / 256, rtol=1e-12)
+    np.testing.assert_array_equal(Us, wl["U0"])
+    np.testing.assert_array_equal(U[:-1], wl["U0"][1:])
+    np.testing.assert_array_equal(U[-1], wl["U0"][-1])
+    np.testing.assert_array_equal(u0, wl["U0"][0])
+    ref = oracle.step(f32_params(p), _world(wl), wl["x0"], wl["U0"], wl["x_ref"], 1.0, 0)
+    assert abs(S[0] - ref["S"][0]) <= TOL_S * abs(ref["S"][0])
+    c.close()
+
+
+def test_single_sample_returns_that_sample():
+    wl = W.quad_small(K=1, T=20)
+    c, p = _ctrl(wl)
+    c.step(wl["x0"])
+    assert c.weights()[0] == 1.0
+    np.testing.assert_allclose(c.last_optimal(), wl["U0"] + c.noise()[0], rtol=0, atol=1e-6)
+    c.close()
+
+
+def test_temperature_limits():
+    wl = W.quad_small(K=64, T=20)
+    c, _ = _ctrl(wl, **{"lambda": 1e-9})
+    c.step(wl["x0"])
+    k = int(np.argmin(c.costs()))
+    np.testing.assert_allclose(c.last_optimal(), wl["U0"] + c.noise()[k], rtol=0, atol=1e-6)
+    c.close()
+    c, _ = _ctrl(wl, **{"lambda": 1e15})
+    c.step(wl["x0"])
+    np.testing.assert_allclose(c.last_optimal(), wl["U0"] + c.noise().mean(axis=0), rtol=0, atol=1e-6)
+    c.close()
+
+
+def test_numeric_failure_leaves_state_unchanged():
+    from paper_2504_06437_amd import _lib as A
+    wl = W.quad_small(K=128, T=20)
+    c, _ = _ctrl(wl, Q=[3e38] * 6)
+    before = c.get_state()
+    st, u0 = c.step_status(wl["x0"] + np.float32(5.0))
+    assert st == A.E_NUMERIC
+    after = c.get_state()
+    assert after["counter"] == before["counter"]
+    np.testing.assert_array_equal(after["U"], before["U"])
+    np.testing.assert_array_equal(u0, before["U"][0])
+    c.close()
+
+
+def test_invalid_inputs_are_rejected_before_launch():
+    from paper_2504_06437_amd import _lib as A
+    from paper_2504_06437_amd.controller import Controller
+    wl = W.quad_small(K=64, T=20)
+    c, _ = _ctrl(wl)
+    x = wl["x0"].copy()
+    x[2] = np.nan
+    st, _ = c.step_status(x)
+    assert st == A.E_INVALID
+    assert c.get_state()["counter"] == 0
+    with pytest.raises(A.MppiError):
+        c.set_exploration(-1.0)
+    with pytest.raises(A.MppiError):
+        c.set_obstacles(np.array([[1.0, 2.0, -0.5]]))
+    for bad in ({"lambda": 0.0}, {"gamma_b": 1.0}, {"K": 0}, {"h_eps": 0.0}, {"tile_lanes": 3}):
+        p = dict(wl["params"])
+        p.update(bad)
+        with pytest.raises(A.MppiError):
+            Controller(p)
+    c.close()
+
+
+def test_checkpoint_resume_is_bit_identical():
+    wl = W.car(K=512, T=20, J=30)
+    c, _ = _ctrl(wl)
+    c.step(wl["x0"])
+    saved = c.get_state()
+    u_a = c.step(wl["x0"])
+    U_a, S_a = c.controls(), c.costs()
+    c.set_state(saved)
+    u_b = c.step(wl["x0"])
+    np.testing.assert_array_equal(u_a, u_b)
+    np.testing.assert_array_equal(U_a, c.controls())
+    np.testing.assert_array_equal(S_a, c.costs())
+    c.close()
+
+
+def test_async_device_step_matches_sync_step():
+    from paper_2504_06437_amd.hip import DeviceArray
+    wl = W.quad_small(K=256, T=20)
+    a, _ = _ctrl(wl)
+    b, _ = _ctrl(wl)
+    ua = a.step(wl["x0"])
+    ua2 = a.step(wl["x0"] + np.float32(0.01))
+    x0 = DeviceArray.from_numpy(np.stack([wl["x0"], wl["x0"] + np.float32(0.01)]))
+    u0 = DeviceArray((2, 2))
+    b.step_async(x0.at(0), u0.at(0))
+    b.step_async(x0.at(1), u0.at(1))
+    assert b.synchronize() == 0
+    got = u0.numpy()
+    np.testing.assert_array_equal(ua, got[0])
+    np.testing.assert_array_equal(ua2, got[1])
+    np.testing.assert_array_equal(a.controls(), b.controls())
+    a.close()
+    b.close()
