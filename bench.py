@@ -119,7 +119,7 @@ def bench_plain(wl, steps, warmup):
         "ms_per_step": 1e3 * wall / steps, "rollout_ms_mean": prof["rollout_ms"] / max(prof["iterations"], 1),
         "update_ms_mean": prof["update_ms"] / max(prof["iterations"], 1), "profiled": prof["iterations"],
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99), "n": len(lat)},
-        "tile_lanes": info["tile_lanes"], "tiles": info["tiles"],
+        "tile_samples": info["tile_samples"], "tiles": info["tiles"],
     }
 
 
@@ -222,7 +222,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload, "K": p["K"], "T": p["T"], "obstacles": J, "shape_points": len(p["shape"]),
-                   "tile_lanes": r["tile_lanes"], "tiles": r["tiles"], "normaliser": "fp32 (fp64 when |rho|/lambda>=1024)"},
+                   "tile_samples": r["tile_samples"], "tiles": r["tiles"], "normaliser": "fp32 (fp64 when |rho|/lambda>=1024)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": load_traffic("rollout", workload),

@@ -77,8 +77,9 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *  - Q, Qf: diagonal running and terminal weights on (x - x_ref).
  *  - shape[P][2]: body-frame shape points (along the heading, normal to it).
  *  - u_min/u_max: actuator limits, applied inside the dynamics.
- *  - tile_lanes: lanes that share one sample's obstacle loop (1, 2, 4, 8 or
- *    16); 0 lets the autotuner choose (per model, K, T, J, P).
+ *  - h_eps in [1e-9, 1e6].
+ *  - tile_samples: samples per rollout workgroup (16, 32, 64, 128 or 256);
+ *    0 lets the autotuner choose (per model, K, T, J, P).
  */
 typedef struct mppi_config {
     uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
@@ -96,7 +97,7 @@ typedef struct mppi_config {
     uint64_t seed;                 /* Philox key */
     int32_t normaliser;            /* mppi_normaliser */
     int32_t init_mode;             /* mppi_init_mode */
-    int32_t tile_lanes;            /* 0 = autotune */
+    int32_t tile_samples;          /* 0 = autotune */
     int32_t reserved[7];           /* must be zero */
 } mppi_config;
 
@@ -125,7 +126,7 @@ typedef struct mppi_step_info {
     double eta;                    /* sum_k exp(-(S_k - rho)/lambda) */
     float beta0;                   /* fused barrier at x0 */
     float beta_d;                  /* fused barrier at x_d = x_ref[T] */
-    int32_t tile_lanes;            /* lanes per sample used */
+    int32_t tile_samples;          /* samples per rollout workgroup used */
     int32_t tiles;                 /* sample tiles per iteration */
 } mppi_step_info;
 

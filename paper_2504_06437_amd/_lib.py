@@ -51,7 +51,7 @@ class Config(ctypes.Structure):
         ("Q", ctypes.c_float * NMAX), ("Qf", ctypes.c_float * NMAX),
         ("P", ctypes.c_int32), ("shape", (ctypes.c_float * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("normaliser", ctypes.c_int32), ("init_mode", ctypes.c_int32),
-        ("tile_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("tile_samples", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -67,7 +67,7 @@ class State(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("counter", ctypes.c_uint64), ("status", ctypes.c_int32), ("fp64_tiles", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("eta", ctypes.c_double), ("beta0", ctypes.c_float),
-                ("beta_d", ctypes.c_float), ("tile_lanes", ctypes.c_int32), ("tiles", ctypes.c_int32)]
+                ("beta_d", ctypes.c_float), ("tile_samples", ctypes.c_int32), ("tiles", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

@@ -53,7 +53,7 @@ def make_config(params: dict) -> A.Config:
     c.seed = int(params["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.normaliser = A.NORMALISER[params.get("normaliser", "auto")]
     c.init_mode = A.INIT_MODE[params.get("init_mode", "repeat")]
-    c.tile_lanes = int(params.get("tile_lanes", 0))
+    c.tile_samples = int(params.get("tile_samples", 0))
     return c
 
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -24,10 +25,10 @@ void set_global_error(const std::string& s) { g_error = s; }
 const char* global_error() { return g_error.c_str(); }
 
 // ---------------------------------------------------------------------------
-// Autotuner: lanes per sample G for a (model, K, T, J, P) shape.  Candidates
-// are timed on the controller's own data with scratch outputs; the choice is
-// cached per shape for the process, so every controller of one shape (alone
-// or in a batch) runs the same tile shape.
+// Autotuner: samples per tile S for a (model, K, T, J, P, costmap) shape.
+// Candidates are timed on the controller's own data with scratch outputs; the
+// choice is cached per shape for the process, so every controller of one
+// shape (alone or in a batch) runs the same tile shape.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -41,12 +42,11 @@ bool autotune_enabled()
     return !(v && v[0] == '0');
 }
 
-// Time the rollout kernel of `h` with G lanes per sample; returns ms or -1.
-float time_rollout(mppi_ctrl* h, int G, int reps)
+// Time the rollout kernel of `h` with S samples per tile; returns ms or -1.
+float time_rollout(mppi_ctrl* h, int S, int reps)
 {
     DevParams q = h->p;
-    q.G = G;
-    q.spt = kBlock / G;
+    q.spt = S;
     q.tiles = (q.K + q.spt - 1) / q.spt;
     const size_t tiles = (size_t)q.tiles;
     void* buf = nullptr;
@@ -74,12 +74,12 @@ float time_rollout(mppi_ctrl* h, int G, int reps)
     q.res = nullptr;
     float best = -1.0f;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool ok = hipMemcpyAsync(q.st, h->p.st, sizeof(CtrlState), hipMemcpyDeviceToDevice, h->stream) == hipSuccess &&
-              hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     StepArgs a;
     std::memset(&a, 0, sizeof a);
+    a.parity = h->iter & 1u;
     for (int r = 0; ok && r <= reps; ++r) {
-        // keep the copy's ticket and iteration parity where the real state has them
+        // a fresh copy of the real state for every run
         ok = hipMemcpyAsync(q.st, h->p.st, sizeof(CtrlState), hipMemcpyDeviceToDevice, h->stream) == hipSuccess;
         ok = ok && hipEventRecord(e0, h->stream) == hipSuccess;
         ok = ok && launch_rollout(q, a, h->stream) == hipSuccess;
@@ -101,7 +101,7 @@ float time_rollout(mppi_ctrl* h, int G, int reps)
 
 namespace dbas {
 
-int choose_tile_lanes(mppi_ctrl* h)
+int choose_tile_samples(mppi_ctrl* h)
 {
     const DevParams& p = h->p;
     const ShapeKey key{p.model, p.K, p.T, p.J, p.P, p.sdf != nullptr ? 1 : 0};
@@ -110,19 +110,20 @@ int choose_tile_lanes(mppi_ctrl* h)
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) return it->second;
     }
-    int G = heuristic_tile_lanes(p.K, p.J);
+    int S = heuristic_tile_samples(p.K, p.J, p.T, p.n);
     if (autotune_enabled() && p.J > 0 && h->sync() == MPPI_OK) {
         float best = -1.0f;
-        for (int cand : {1, 2, 4, 8, 16}) {
+        for (int cand : {16, 32, 64, 128, 256}) {
+            if (tile_chunk_slots(p.J, p.T, p.n, cand) == 0 || (p.K + cand - 1) / cand > kMaxTiles) continue;
             const float ms = time_rollout(h, cand, 3);
             if (ms > 0 && (best < 0 || ms < best * 0.97f)) {
                 best = ms;
-                G = cand;
+                S = cand;
             }
         }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache.emplace(key, G);
+    g_tune_cache.emplace(key, S);
     return g_tune_cache[key];
 }
 
@@ -142,8 +143,8 @@ struct mppi_batch {
     BatchUnit* d_units = nullptr;
     RowUnit* d_rows = nullptr;
     uint32_t* d_queue = nullptr;
-    float* d_x0s = nullptr;
-    float* h_x0s = nullptr;        // pinned staging of the per-step states
+    BatchIn* d_in = nullptr;
+    BatchIn* h_in = nullptr;        // pinned staging of the per-step states and buffer parities
     int nunits = 0, nrows = 0, grid = 0;
     size_t lds = 0;
     hipGraph_t graph = nullptr;
@@ -156,9 +157,9 @@ struct mppi_batch {
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (void* p : {(void*)d_params, (void*)d_units, (void*)d_rows, (void*)d_queue, (void*)d_x0s})
+        for (void* p : {(void*)d_params, (void*)d_units, (void*)d_rows, (void*)d_queue, (void*)d_in})
             if (p) (void)hipFree(p);
-        if (h_x0s) (void)hipHostFree(h_x0s);
+        if (h_in) (void)hipHostFree(h_in);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 
@@ -188,11 +189,11 @@ struct mppi_batch {
             params[c] = ctrls[c]->p;
             versions[c] = ctrls[c]->version;
             const DevParams& p = params[c];
-            lds_max = std::max(lds_max, tile_lds_bytes(p.J, p.T, p.n));
+            lds_max = std::max(lds_max, tile_lds_bytes(p.J, p.T, p.n, p.spt));
             // longest-processing-time order: per-tile work ~ samples x steps x (pairs + fixed)
-            const double cost = (double)std::min(p.spt, p.K) * p.T * ((double)p.P * p.J / p.G + 64.0);
+            const double cost = (double)std::min(p.spt, p.K) * p.T * ((double)p.P * p.J + 64.0);
             for (int t = 0; t < p.tiles; ++t) work.push_back({cost, BatchUnit{c, t}});
-            for (int r = 0; r < 2 * p.T; r += kRowsPerBlock) rows.push_back(RowUnit{c, r});
+            for (int r = 0; r < 2 * p.T; r += kUpdBlock / kWave) rows.push_back(RowUnit{c, r});
         }
         std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         std::vector<BatchUnit> units(work.size());
@@ -217,11 +218,11 @@ struct mppi_batch {
         if ((st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "CU count"))) return st;
         grid = std::max(1, std::min(nunits, cus * batch_rollout_blocks_per_cu(lds)));
 
-        // capture: states H2D, persistent rollout, row update
+        // capture: per-step inputs H2D, persistent rollout, row update
         if ((st = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture"))) return st;
-        hipError_t e = hipMemcpyAsync(d_x0s, h_x0s, sizeof(float) * (MPPI_NMAX + 2) * n, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = launch_batch_rollout(d_params, d_units, nunits, d_x0s, d_queue, grid, lds, stream);
-        if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, nullptr, stream);
+        hipError_t e = hipMemcpyAsync(d_in, h_in, sizeof(BatchIn) * n, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_batch_rollout(d_params, d_units, nunits, d_in, d_queue, grid, lds, stream);
+        if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, d_in, nullptr, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip(e, "captured launch"); }
@@ -244,6 +245,12 @@ extern "C" int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_dev
             delete b;
             return MPPI_E_INVALID;
         }
+        for (int d = 0; d < c; ++d)
+            if (ctrls[d] == ctrls[c]) {
+                set_global_error("mppi_batch_create: a controller appears twice");
+                delete b;
+                return MPPI_E_INVALID;
+            }
         b->ctrls.push_back(ctrls[c]);
     }
     int st = MPPI_OK;
@@ -257,11 +264,10 @@ extern "C" int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_dev
         if (!st) st = c->sync();
     if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2), "hipMalloc queue");
     if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2), "queue init");
-    if (!st) st = b->hip(hipMalloc(&b->d_x0s, sizeof(float) * (MPPI_NMAX + 2) * n), "hipMalloc x0s");
-    if (!st) st = b->hip(hipHostMalloc(reinterpret_cast<void**>(&b->h_x0s), sizeof(float) * (MPPI_NMAX + 2) * n, 0),
-                         "hipHostMalloc x0s");
+    if (!st) st = b->hip(hipMalloc(&b->d_in, sizeof(BatchIn) * n), "hipMalloc inputs");
+    if (!st) st = b->hip(hipHostMalloc(reinterpret_cast<void**>(&b->h_in), sizeof(BatchIn) * n, 0), "hipHostMalloc inputs");
     if (!st) {
-        std::memset(b->h_x0s, 0, sizeof(float) * (MPPI_NMAX + 2) * n);
+        std::memset(b->h_in, 0, sizeof(BatchIn) * n);
         st = b->build();
     }
     if (st) {
@@ -289,18 +295,21 @@ extern "C" int mppi_batch_step(mppi_batch_t* b, const float* x0s, float* u0s, in
             if (!std::isfinite(x0s[(size_t)c * MPPI_NMAX + a])) return b->fail(MPPI_E_INVALID, "non-finite x0");
         if (h->version != b->versions[c]) stale = true;
     }
+    // a controller's own stream may still hold work of a standalone step
+    for (mppi_ctrl* h : b->ctrls)
+        if ((st = h->sync())) return b->fail(st, h->err);
     if (stale) {
-        for (mppi_ctrl* h : b->ctrls)
-            if ((st = h->sync())) return b->fail(st, h->err);
         if ((st = b->hip(hipStreamSynchronize(b->stream), "sync"))) return st;
         if ((st = b->build())) return st;
     }
     for (int c = 0; c < n; ++c) {
-        float* row = b->h_x0s + (size_t)c * (MPPI_NMAX + 2);
-        std::memset(row, 0, sizeof(float) * (MPPI_NMAX + 2));
-        std::memcpy(row, x0s + (size_t)c * MPPI_NMAX, sizeof(float) * b->ctrls[c]->p.n);
+        BatchIn& in = b->h_in[c];
+        std::memset(&in, 0, sizeof in);
+        std::memcpy(in.x0, x0s + (size_t)c * MPPI_NMAX, sizeof(float) * b->ctrls[c]->p.n);
+        in.parity = b->ctrls[c]->iter & 1u;
     }
     if ((st = b->hip(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"))) return st;
+    for (mppi_ctrl* h : b->ctrls) ++h->iter;
     if ((st = b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize"))) return st;
     int first = MPPI_OK;
     for (int c = 0; c < n; ++c) {

@@ -10,10 +10,12 @@
 
 namespace dbas {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 constexpr int kWave = 64;
+constexpr int kRollBlock = 1024;     // rollout workgroup: 16 wave64s, one tile of S samples
+constexpr int kUpdBlock = 256;       // update workgroup: 4 wave64s, one control row each
+constexpr int kMaxTiles = 4096;      // most sample tiles per controller
+constexpr int kMaxTile = 256;        // largest S
 constexpr int kM = MPPI_M;
-constexpr int kRowsPerBlock = kBlock / kWave;   // update kernel: one wave per control row
 
 // Mutable per-controller state, resident in device memory.
 struct CtrlState {
@@ -24,8 +26,8 @@ struct CtrlState {
     float S_e;               // exploration rate
     int32_t status;          // status of the last iteration
     float beta0, beta_d;     // fused barrier at x0 and at x_d
-    uint32_t tiles_done;     // completion ticket of the running iteration
-    uint32_t iter;           // iterations run; U[iter & 1] is the warm start
+    uint32_t reserved0;
+    uint32_t iter;           // iterations run (the host tracks the same count)
     int32_t fp64_tiles;      // tiles of the last iteration whose weights ran in FP64
     int32_t pad;
 };
@@ -41,7 +43,7 @@ struct HostResult {
 // Everything a kernel needs to run one controller's iteration.  Passed by
 // value to the single-controller kernels, held in an array for the batch.
 struct DevParams {
-    int32_t model, K, Kp, T, P, J, G, spt, tiles, n;
+    int32_t model, K, Kp, T, P, J, spt, tiles, n;   // spt: samples per tile (S)
     int32_t normaliser, init_mode;
     float dt, mass, gravity, arm, inertia, wheelbase;
     float u_min[kM], u_max[kM], sigma[kM];
@@ -74,12 +76,14 @@ struct StepArgs {
     float x0[MPPI_NMAX + 2];
     const float* x0_ptr;     // device x0 (overrides x0[] when non-null)
     float* u0_dev;           // optional device u0 output
+    uint32_t parity;         // iterations run & 1: the half of U that holds the warm start
 };
 
-// One unit of the batched rollout: sample tile `tile` of controller `ctrl`.
-struct BatchUnit {
-    int32_t ctrl;
-    int32_t tile;
+// Per-step input of one controller of a batch (staged by the host).
+struct BatchIn {
+    float x0[MPPI_NMAX + 2];
+    uint32_t parity;
+    uint32_t pad[3];
 };
 
 // One unit of the batched update: control rows [row0, row0 + 4) of `ctrl`.
@@ -88,32 +92,64 @@ struct RowUnit {
     int32_t row0;
 };
 
+// One unit of the batched rollout: sample tile `tile` of controller `ctrl`.
+struct BatchUnit {
+    int32_t ctrl;
+    int32_t tile;
+};
+
 inline int state_dim(int model) { return model == MPPI_QUAD6 ? 6 : model == MPPI_QUAD5 ? 5 : 4; }
 
-// Dynamic LDS bytes one rollout tile of this controller needs.
-inline size_t tile_lds_bytes(int J, int T, int n)
+// LDS obstacle slots (at least one, so the carve-up never has a zero-size array).
+__host__ __device__ inline int obstacle_slots(int J) { return J > 0 ? J : 1; }
+
+constexpr size_t kLdsLimit = 65536;     // dynamic LDS budget of one rollout workgroup
+constexpr int kChunkSlotsMax = 2048;    // (step, sample) input slots staged per chunk
+
+// LDS bytes of a rollout tile apart from the chunk's input slots.
+__host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
 {
     size_t b = 0;
-    b += (size_t)(J > 0 ? J : 1) * 16;          // obstacles, local frame
+    b += (size_t)obstacle_slots(J) * 16;        // obstacles, local frame
     b += (size_t)T * 8;                         // U
     b += (size_t)(T + 1) * n * 4;               // reference, local frame
     b = (b + 15) & ~(size_t)15;
-    b += (size_t)kBlock * 8;                    // tile exponentials
+    b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
     return b;
+}
+
+constexpr int kSlotBytes = 32;          // per (step, sample): inputs (float4) + pose (float4)
+
+// (step, sample) slots per horizon chunk: a whole number of steps for the
+// tile's S samples, within the LDS budget.  0 when even one step does not fit
+// (such a configuration is rejected).
+__host__ __device__ inline int tile_chunk_slots(int J, int T, int n, int S)
+{
+    const size_t fixed = tile_fixed_lds(J, T, n);
+    if (fixed + (size_t)S * kSlotBytes > kLdsLimit) return 0;
+    long slots = (long)((kLdsLimit - fixed) / kSlotBytes);
+    if (slots > kChunkSlotsMax) slots = kChunkSlotsMax;
+    if (slots > (long)T * S) slots = (long)T * S;
+    return (int)(slots / S * S);
+}
+
+// Dynamic LDS bytes one rollout tile of this controller needs.
+inline size_t tile_lds_bytes(int J, int T, int n, int S)
+{
+    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_slots(J, T, n, S) * kSlotBytes;
 }
 
 // Kernel launchers (mppi_kernels.hip).
 hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch_rollout(const DevParams* d_params, const BatchUnit* d_units, int nunits,
-                                const float* d_x0s, uint32_t* d_queue, int grid, size_t lds,
-                                hipStream_t s);
-hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits,
+                                const BatchIn* d_in, uint32_t* d_queue, int grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, const BatchIn* d_in,
                                float* d_u0s, hipStream_t s);
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s);
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s);
 int batch_rollout_blocks_per_cu(size_t lds);
-bool tile_lanes_supported(int G);
+bool tile_samples_supported(int S);
 
 }  // namespace dbas

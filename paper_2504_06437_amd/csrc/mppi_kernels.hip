@@ -1,26 +1,37 @@
 // HIP kernels (gfx950) of one DBaS-Log-MPPI iteration.
 //
-//   rollout kernel  -- one workgroup per sample tile.  Each sample is owned by
-//                      a group of G lanes (G = 1: one sample per lane).  Per
-//                      step: Philox4x32-10 + normal x log-normal noise (Sec.
-//                      IV-C, shared across the group), the dynamics (eq.
-//                      veh_dyn) with saturated inputs, the fused barrier over
-//                      the obstacles (staged in LDS, split across the group)
-//                      and the costmap, the barrier-state recursion (eq.
-//                      barrier_update) and the running cost (Alg. 1, eq.
-//                      cost-to-go_bas) in a compensated FP32 sum.  The tile
-//                      then forms its own min-shifted exponentials and the
-//                      tile sums  eta_b = sum e_k,  N_b[t][c] = sum e_k du_k,
-//                      and the last tile to finish merges the tile minima and
-//                      normalisers (eq. control_update: rho = min S, eta).
-//   update kernel   -- one wave per control row (t, c): U*[t][c] = U[t][c] +
-//                      sum_b f_b N_b[t][c] / eta, coalesced over tiles; writes
-//                      U* and the shifted warm start (Alg. 1 closing loop)
-//                      into the other half of a double buffer, and u0*.
+//   rollout kernel  -- one workgroup per tile of S samples.  The horizon is
+//                      processed in chunks of steps, each in four phases:
+//                       (1) inputs: the whole workgroup draws the chunk's
+//                           Philox4x32-10 normal x log-normal noise (Sec. IV-C)
+//                           for every (step, sample) and turns it into the
+//                           state-independent terms (saturated inputs, their
+//                           model terms, the control cost of Alg. 1), in LDS;
+//                       (2) dynamics: one lane per sample integrates the state
+//                           (eq. veh_dyn), storing the pose of every step and
+//                           adding the tracking and control costs;
+//                       (3) barrier: every thread takes (step, sample) items
+//                           and evaluates the fused barrier over the obstacles
+//                           (LDS broadcast) and the costmap -- the bulk of the
+//                           work, with no dependence between items;
+//                       (4) barrier state: one lane per sample runs the
+//                           recursion of eq. barrier_update and adds R_B beta
+//                           (Alg. 1, eq. cost-to-go_bas) to its compensated
+//                           FP32 cost.
+//                      The tile then forms its own min-shifted exponentials and
+//                      the tile sums eta_b = sum e_k and N_b[t][c] =
+//                      sum e_k du_k.  Tiles never wait for one another.
+//   update kernel   -- one workgroup per controller: merges the tile minima
+//                      and normalisers (eq. control_update: rho = min S, eta),
+//                      then one wave per control row (t, c): U*[t][c] =
+//                      U[t][c] + sum_b f_b N_b[t][c] / eta, coalesced over
+//                      tiles; writes U* and the shifted warm start (Alg. 1
+//                      closing loop) into the other half of a double buffer,
+//                      and u0*.
 //
-// All positions are handled in a frame centred on the iteration's start
-// position (obstacles, reference and costmap offset are translated once in
-// FP64), so FP32 rounding is relative to the rollout's extent, not the world's.
+// Positions are handled in a frame centred on the iteration's start position
+// (obstacles, reference and costmap offset are translated once in FP64), so
+// FP32 rounding is relative to the rollout's extent, not the world's.
 #include "mppi_internal.hpp"
 
 #include <math.h>
@@ -68,33 +79,37 @@ __device__ __forceinline__ float2 nln_pair(uint4 r, float scale0, float scale1, 
     return o;
 }
 
+// sin and cos of a heading.  Cody-Waite reduction by pi/2 (three-part split
+// of pi/2, each product exact inside an FMA) to |r| <= pi/4, then the Taylor
+// series of sin to r^9 and of cos to r^10 (truncation < 3e-9 on |r| <= pi/4,
+// below half an FP32 ulp), and the quadrant's swap and signs.  Headings
+// beyond 4096 quarter turns fall back to the library routine.
+__device__ __forceinline__ void heading_sincos(float x, float& s, float& c)
+{
+    const float k = rintf(x * 0.63661975f);
+    if (fabsf(k) > 4096.0f) {
+        sincosf(x, &s, &c);
+        return;
+    }
+    float r = fmaf(-k, 1.5707963705062866f, x);
+    r = fmaf(-k, -4.371138828673793e-08f, r);
+    r = fmaf(-k, -1.7151245100058819e-15f, r);
+    const float r2 = r * r;
+    const float ps = r2 * fmaf(r2, fmaf(r2, fmaf(r2, 2.7557319e-06f, -1.9841270e-04f), 8.3333333e-03f),
+                               -1.6666667e-01f);
+    const float sr = fmaf(r, ps, r);
+    const float pc = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -2.7557319e-07f, 2.4801587e-05f), -1.3888889e-03f),
+                                             4.1666667e-02f), -0.5f), 1.0f);
+    const int q = (int)k & 3;
+    const float a = (q & 1) ? pc : sr;
+    const float b = (q & 1) ? sr : pc;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
 // ---------------------------------------------------------------------------
-// Cross-lane helpers.
+// Reductions.
 // ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over a group of G adjacent lanes (G <= 16, inside one DPP row).  Every
-// lane of the group ends with the same bits: each stage adds a lane's value
-// to its partner's, and IEEE addition is commutative.
-template <int G>
-__device__ __forceinline__ float group_sum(float v)
-{
-    if constexpr (G >= 2) v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
-    if constexpr (G >= 4) v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
-    if constexpr (G >= 8) v += dpp<0x141>(v);   // row_half_mirror
-    if constexpr (G >= 16) v += dpp<0x140>(v);  // row_mirror
-    return v;
-}
-
-__device__ __forceinline__ float lane_read(float v, int src_lane)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
-}
-
 __device__ __forceinline__ float wave_sum_f(float v)
 {
 #pragma unroll
@@ -116,7 +131,9 @@ __device__ __forceinline__ double wave_min_d(double v)
     return v;
 }
 
-// Block reductions (256 threads); every thread gets the result.
+// Block reductions over NW waves; every thread gets the result.  slots
+// holds at least NW doubles.
+template <int NW>
 __device__ __forceinline__ double block_min_d(double v, double* slots)
 {
     v = wave_min_d(v);
@@ -125,10 +142,11 @@ __device__ __forceinline__ double block_min_d(double v, double* slots)
     __syncthreads();
     double r = slots[0];
 #pragma unroll
-    for (int i = 1; i < kBlock / kWave; ++i) r = fmin(r, slots[i]);
+    for (int i = 1; i < NW; ++i) r = fmin(r, slots[i]);
     return r;
 }
 
+template <int NW>
 __device__ __forceinline__ double block_sum_d(double v, double* slots)
 {
     v = wave_sum_d(v);
@@ -137,10 +155,11 @@ __device__ __forceinline__ double block_sum_d(double v, double* slots)
     __syncthreads();
     double r = slots[0];
 #pragma unroll
-    for (int i = 1; i < kBlock / kWave; ++i) r += slots[i];
+    for (int i = 1; i < NW; ++i) r += slots[i];
     return r;
 }
 
+template <int NW>
 __device__ __forceinline__ float block_sum_f(float v, double* slots)
 {
     v = wave_sum_f(v);
@@ -149,7 +168,7 @@ __device__ __forceinline__ float block_sum_f(float v, double* slots)
     __syncthreads();
     float r = (float)slots[0];
 #pragma unroll
-    for (int i = 1; i < kBlock / kWave; ++i) r += (float)slots[i];
+    for (int i = 1; i < NW; ++i) r += (float)slots[i];
     return r;
 }
 
@@ -164,9 +183,49 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x)
     lo += err;
 }
 
+// ---------------------------------------------------------------------------
+// Barrier terms.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ float barrier_rcp(float h, float eps)
 {
     return __builtin_amdgcn_rcpf(fmaxf(h, eps));
+}
+
+// h clamped to [eps, kHMax]: the lower end is the barrier's own cap
+// B = 1/max(h, eps); the upper end (h = 1e9 m^2, 31 km) keeps the products of
+// four clamped values below the FP32 range while changing B by < 1e-9.
+constexpr float kHMax = 1e9f;
+
+__device__ __forceinline__ float clamp_h(float h, float eps)
+{
+    return __builtin_amdgcn_fmed3f(h, eps, kHMax);
+}
+
+// sum_i 1/h_i for N clamped values, taken four at a time as one fraction
+// ((a+b)cd + (c+d)ab) / (abcd) -- exact up to rounding, all terms positive,
+// one reciprocal per four -- alternating between two accumulators.
+template <int N>
+__device__ __forceinline__ void reciprocal_sum(const float* h, float& acc, float& acc2)
+{
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i + 4 <= N; i += 4, ++k) {
+        const float ab = h[i] * h[i + 1], cd = h[i + 2] * h[i + 3];
+        const float num = fmaf(h[i] + h[i + 1], cd, (h[i + 2] + h[i + 3]) * ab);
+        float& a = (k & 1) ? acc2 : acc;
+        a = fmaf(num, __builtin_amdgcn_rcpf(ab * cd), a);
+    }
+    constexpr int r = N % 4;
+    constexpr int i = N - r;
+    float& a = (k & 1) ? acc2 : acc;
+    if constexpr (r == 3) {
+        const float ab = h[i] * h[i + 1];
+        a = fmaf(fmaf(h[i] + h[i + 1], h[i + 2], ab), __builtin_amdgcn_rcpf(ab * h[i + 2]), a);
+    } else if constexpr (r == 2) {
+        a = fmaf(h[i] + h[i + 1], __builtin_amdgcn_rcpf(h[i] * h[i + 1]), a);
+    } else if constexpr (r == 1) {
+        a += __builtin_amdgcn_rcpf(h[i]);
+    }
 }
 
 // Bilinear costmap sample between cell centres, clamped to the edge cells.
@@ -186,27 +245,33 @@ __device__ __forceinline__ float sdf_sample(const float* __restrict__ sdf, int W
 }
 
 // ---------------------------------------------------------------------------
-// Models (explicit Euler, inputs saturated inside f).  sth/cth are the sine
-// and cosine of the *old* heading.
+// Models (explicit Euler, inputs saturated inside f).  inputs() turns the
+// saturated controls into the model's state-independent terms (f0, f1);
+// step() advances the state with them, using the sine and cosine of the *old*
+// heading.
 // ---------------------------------------------------------------------------
 template <int MODEL> struct Model;
 
 template <> struct Model<MPPI_QUAD6> {
     static constexpr int NS = 6;
-    // state (x, z, theta, vx, vz, omega); inputs: rotor thrust deviations.
-    __device__ static __forceinline__ void step(const DevParams& p, float* x, float s0, float s1,
-                                                float sth, float cth)
+    // state (x, z, theta, vx, vz, omega); inputs: rotor thrust deviations from
+    // hover.  f0 = (F1 + F2)/m, f1 = (F2 - F1) arm / I.
+    __device__ static __forceinline__ void inputs(const DevParams& p, float s0, float s1, float& f0, float& f1)
     {
-        const float dt = p.dt;
         const float hover = 0.5f * p.mass * p.gravity;
         const float F1 = hover + s0, F2 = hover + s1;
-        const float acc = (F1 + F2) / p.mass;
+        f0 = (F1 + F2) / p.mass;
+        f1 = (F2 - F1) * (p.arm / p.inertia);
+    }
+    __device__ static __forceinline__ void step(const DevParams& p, float* x, float f0, float f1, float sth, float cth)
+    {
+        const float dt = p.dt;
         const float x0 = x[0] + x[3] * dt;
         const float x1 = x[1] + x[4] * dt;
         const float x2 = x[2] + x[5] * dt;
-        const float x3 = x[3] - acc * sth * dt;
-        const float x4 = x[4] + (acc * cth - p.gravity) * dt;
-        const float x5 = x[5] + (F2 - F1) * (p.arm / p.inertia) * dt;
+        const float x3 = x[3] - f0 * sth * dt;
+        const float x4 = x[4] + (f0 * cth - p.gravity) * dt;
+        const float x5 = x[5] + f1 * dt;
         x[0] = x0; x[1] = x1; x[2] = x2; x[3] = x3; x[4] = x4; x[5] = x5;
     }
 };
@@ -214,16 +279,20 @@ template <> struct Model<MPPI_QUAD6> {
 template <> struct Model<MPPI_QUAD5> {
     static constexpr int NS = 5;
     // Sec. V-A: state (x, z, theta, vx, vz); inputs (pitch rate, throttle).
-    __device__ static __forceinline__ void step(const DevParams& p, float* x, float s0, float s1,
-                                                float sth, float cth)
+    // f0 = pitch rate, f1 = (m g + u_t)/m.
+    __device__ static __forceinline__ void inputs(const DevParams& p, float s0, float s1, float& f0, float& f1)
+    {
+        f0 = s0;
+        f1 = (p.mass * p.gravity + s1) / p.mass;
+    }
+    __device__ static __forceinline__ void step(const DevParams& p, float* x, float f0, float f1, float sth, float cth)
     {
         const float dt = p.dt;
-        const float acc = (p.mass * p.gravity + s1) / p.mass;
         const float x0 = x[0] + x[3] * dt;
         const float x1 = x[1] + x[4] * dt;
-        const float x2 = x[2] + s0 * dt;
-        const float x3 = x[3] - acc * sth * dt;
-        const float x4 = x[4] + (acc * cth - p.gravity) * dt;
+        const float x2 = x[2] + f0 * dt;
+        const float x3 = x[3] - f1 * sth * dt;
+        const float x4 = x[4] + (f1 * cth - p.gravity) * dt;
         x[0] = x0; x[1] = x1; x[2] = x2; x[3] = x3; x[4] = x4;
     }
 };
@@ -231,58 +300,73 @@ template <> struct Model<MPPI_QUAD5> {
 template <> struct Model<MPPI_CAR> {
     static constexpr int NS = 4;
     // Sec. V-B Ackermann model: state (x, y, theta, v); inputs (steer, accel).
-    __device__ static __forceinline__ void step(const DevParams& p, float* x, float s0, float s1,
-                                                float sth, float cth)
+    // f0 = tan(phi)/L, f1 = a.
+    __device__ static __forceinline__ void inputs(const DevParams& p, float s0, float s1, float& f0, float& f1)
+    {
+        f0 = tanf(s0) / p.wheelbase;
+        f1 = s1;
+    }
+    __device__ static __forceinline__ void step(const DevParams& p, float* x, float f0, float f1, float sth, float cth)
     {
         const float dt = p.dt;
         const float v = x[3];
         const float x0 = x[0] + v * cth * dt;
         const float x1 = x[1] + v * sth * dt;
-        const float x2 = x[2] + v * tanf(s0) / p.wheelbase * dt;
-        const float x3 = x[3] + s1 * dt;
+        const float x2 = x[2] + v * f0 * dt;
+        const float x3 = x[3] + f1 * dt;
         x[0] = x0; x[1] = x1; x[2] = x2; x[3] = x3;
     }
 };
 
-// LDS carve-up of one rollout tile.
+// LDS carve-up of one rollout tile (sizes: tile_fixed_lds + chunk slots).
 struct TileLds {
     float4* obs;     // [J] (ox, oy, -r^2, 0), local frame
     float2* U;       // [T]
     float* ref;      // [(T+1) n], local frame
-    double* e;       // [kBlock]
-    double* slots;   // [16]
+    double* e;       // [kMaxTile] tile exponentials
+    double* slots;   // [16] block-reduction slots
+    float4* in;      // [chunk] per (step, sample): (f0, f1, control cost, 0); then barrier partial sums
+    float4* pose;    // [chunk] per (step, sample): (x, y, cos theta, sin theta)
 };
 
-__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n)
+__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int chunk)
 {
     TileLds L;
     size_t off = 0;
     L.obs = reinterpret_cast<float4*>(smem + off);
-    off += (size_t)(J > 0 ? J : 1) * 16;
+    off += (size_t)obstacle_slots(J) * 16;
     L.U = reinterpret_cast<float2*>(smem + off);
     off += (size_t)T * 8;
     L.ref = reinterpret_cast<float*>(smem + off);
     off += (size_t)(T + 1) * n * 4;
     off = (off + 15) & ~(size_t)15;
     L.e = reinterpret_cast<double*>(smem + off);
-    off += (size_t)kBlock * 8;
+    off += (size_t)kMaxTile * 8;
     L.slots = reinterpret_cast<double*>(smem + off);
+    off += 16 * 8;
+    L.in = reinterpret_cast<float4*>(smem + off);
+    off += (size_t)chunk * 16;
+    L.pose = reinterpret_cast<float4*>(smem + off);
     return L;
 }
 
 struct X0 {
     float v[MPPI_NMAX + 2];
+    uint32_t parity;     // which half of the warm-start double buffer holds U
 };
+
+constexpr int kRollWaves = kRollBlock / kWave;
+constexpr int kUpdWaves = kUpdBlock / kWave;
 
 // Fused barrier of a (local-frame) pose, cooperatively over the block.
 __device__ float fused_barrier_block(const DevParams& p, const TileLds& L, int P, float px0, float py0, float th,
                                      float inv_res, float offx, float offy)
 {
     float sth, cth;
-    sincosf(th, &sth, &cth);
+    heading_sincos(th, sth, cth);
     float acc = 0.0f;
     const int J = p.J;
-    for (int idx = threadIdx.x; idx < P * J; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < P * J; idx += kRollBlock) {
         const int i = idx / J, j = idx - i * J;
         const float a = p.shape[i][0], b = p.shape[i][1];
         const float px = px0 + (a * cth - b * sth);
@@ -299,34 +383,90 @@ __device__ float fused_barrier_block(const DevParams& p, const TileLds& L, int P
         acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
                            p.h_eps);
     }
-    return block_sum_f(acc, L.slots);
+    return block_sum_f<kRollWaves>(acc, L.slots);
+}
+
+// Part of the fused barrier of one pose: every shape point against obstacles
+// [j0, j1) (read by LDS broadcast: the lanes of a wave read the same one),
+// plus the costmap terms when `with_map`.
+template <int PT>
+__device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa,
+                                                    const float* sb, float4 pose, int j0, int j1, bool with_map,
+                                                    float inv_res, float offx, float offy)
+{
+    constexpr int PM = PT ? PT : MPPI_PMAX;
+    const float eps = p.h_eps;
+    float px[PM], py[PM];
+#pragma unroll
+    for (int i = 0; i < PM; ++i) {
+        px[i] = pose.x + (sa[i] * pose.z - sb[i] * pose.w);
+        py[i] = pose.y + (sa[i] * pose.w + sb[i] * pose.z);
+    }
+    float acc = 0.0f, acc2 = 0.0f;
+#pragma unroll 2
+    for (int j = j0; j < j1; ++j) {
+        const float4 o = L.obs[j];
+        if constexpr (PT != 0) {
+            float h[PM];
+#pragma unroll
+            for (int i = 0; i < PM; ++i) {
+                const float dx = px[i] - o.x, dy = py[i] - o.y;
+                h[i] = clamp_h(fmaf(dx, dx, fmaf(dy, dy, o.z)), eps);
+            }
+            reciprocal_sum<PM>(h, acc, acc2);
+        } else {
+#pragma unroll
+            for (int i = 0; i < PM; ++i) {
+                if (i < P) {
+                    const float dx = px[i] - o.x, dy = py[i] - o.y;
+                    acc += __builtin_amdgcn_rcpf(clamp_h(fmaf(dx, dx, fmaf(dy, dy, o.z)), eps));
+                }
+            }
+        }
+    }
+    acc += acc2;
+    if (with_map) {
+#pragma unroll
+        for (int i = 0; i < PM; ++i) {
+            if (PT || i < P) {
+                acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px[i], inv_res, offx),
+                                              fmaf(py[i], inv_res, offy)),
+                                   eps);
+            }
+        }
+    }
+    return acc;
 }
 
 // ---------------------------------------------------------------------------
-// One sample tile: rollout, tile softmax partials, last-tile merge.
+// One tile of S samples: rollout and the tile's softmax partials.
 // PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX).
 // ---------------------------------------------------------------------------
-template <int MODEL, int G, int PT>
+template <int MODEL, int S, int PT>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int NS = Model<MODEL>::NS;
     constexpr int PM = PT ? PT : MPPI_PMAX;
+    static_assert(S >= 16 && S <= kMaxTile && (S & (S - 1)) == 0, "tile size");
     const int tid = threadIdx.x;
     const int J = p.J, T = p.T, K = p.K, Kp = p.Kp;
     const int P = PT ? PT : p.P;
-    const TileLds L = carve(smem, J, T, NS);
+    // (step, sample) slots per chunk (the host only configures tiles whose
+    // chunk holds at least one step)
+    const int chunk = tile_chunk_slots(J, T, NS, S);
+    const int tcs = max(1, chunk / S);
+    const TileLds L = carve(smem, J, T, NS, chunk);
 
-    const uint32_t iter = p.st->iter;
-    const float* Uin = p.U + (size_t)(iter & 1u) * T * kM;
+    const float* Uin = p.U + (size_t)(xs.parity & 1u) * T * kM;
 
     // ---- staging: local frame centred on the start position ----
     const double ox = (double)xs.v[0], oy = (double)xs.v[1];
-    for (int j = tid; j < J; j += kBlock) {
+    for (int j = tid; j < J; j += kRollBlock) {
         const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
         L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(-(r * r)), 0.0f);
     }
-    for (int t = tid; t < T; t += kBlock) L.U[t] = make_float2(Uin[2 * t], Uin[2 * t + 1]);
-    for (int i = tid; i < (T + 1) * NS; i += kBlock) {
+    for (int t = tid; t < T; t += kRollBlock) L.U[t] = make_float2(Uin[2 * t], Uin[2 * t + 1]);
+    for (int i = tid; i < (T + 1) * NS; i += kRollBlock) {
         const int a = i % NS;
         const float v = p.xref[i];
         L.ref[i] = a == 0 ? (float)((double)v - ox) : a == 1 ? (float)((double)v - oy) : v;
@@ -345,13 +485,10 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const float beta_d = fused_barrier_block(p, L, P, L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
                                              inv_res, offx, offy);
 
-    // ---- per-lane setup ----
-    const int lane = tid & (kWave - 1);
-    const int g = tid & (G - 1);
-    const int sidx = tid / G;
-    const int k = tile * p.spt + sidx;
-    const bool valid = k < K;
-    const int gbase = lane & ~(G - 1);
+    // ---- setup: lanes 0..S-1 own one sample each ----
+    const bool owner = tid < S;
+    const int k = tile * S + tid;
+    const bool valid = owner && k < K;
 
     const float S_e = p.st->S_e;
     const float sqS = sqrtf(S_e);
@@ -360,7 +497,6 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const float cw1 = p.sigma[1] > 0.0f ? p.gamma_u / (S_e * p.sigma[1] * p.sigma[1]) : 0.0f;
     const uint64_t ctr = p.st->counter;
     const uint32_t c_lo = (uint32_t)ctr, c_hi = (uint32_t)(ctr >> 32);
-    const float eps = p.h_eps;
 
     float x[NS];
     x[0] = 0.0f;
@@ -368,7 +504,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 #pragma unroll
     for (int a = 2; a < NS; ++a) x[a] = xs.v[a];
     float sth, cth;
-    sincosf(x[2], &sth, &cth);
+    heading_sincos(x[2], sth, cth);
     // eq. barrier_update is linear in beta, so beta_t = bv_t + c_t with the
     // sample-dependent part bv_t = b_t + gamma_B bv_{t-1} (bv_0 = beta_0) and
     // the common part c_t = gamma_B (c_{t-1} - beta_d) (c_0 = 0).  The common
@@ -384,7 +520,6 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     }
     float S_hi = 0.0f, S_lo = 0.0f;
-    float my_du0 = 0.0f, my_du1 = 0.0f;
 
     float sa[PM], sb[PM];
 #pragma unroll
@@ -392,87 +527,78 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         sa[i] = (PT || i < P) ? p.shape[i][0] : 0.0f;
         sb[i] = (PT || i < P) ? p.shape[i][1] : 0.0f;
     }
+    float* bpart = reinterpret_cast<float*>(L.in);     // phase 3 output, over the spent inputs
 
-    for (int t = 0; t < T; ++t) {
-        // -- noise (Alg. 1 sampling; Sec. IV-C) --
-        float du0, du1;
-        if constexpr (G == 1) {
-            const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)t, c_lo, c_hi), p.seed_lo, p.seed_hi);
+    for (int t0 = 0; t0 < T; t0 += tcs) {
+        const int tc = min(tcs, T - t0);
+        const int items = tc * S;
+        // barrier items are split over nsp obstacle ranges (1, 2 or 4) when
+        // there are few items, so that every thread has work
+        int nsp = 1;
+        while (nsp < 4 && items * nsp < 2 * kRollBlock && J >= 16 * nsp) nsp *= 2;
+        __syncthreads();
+        // (1) inputs of every (step, sample) of the chunk
+        for (int idx = tid; idx < items; idx += kRollBlock) {
+            const int s = idx & (S - 1), tt = idx / S;
+            const int t = t0 + tt;
+            const int kk = tile * S + s;
+            const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), p.seed_lo, p.seed_hi);
             const float2 z = nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
-            du0 = z.x;
-            du1 = z.y;
-            if (valid) {
-                p.du[(size_t)(2 * t) * Kp + k] = du0;
-                p.du[(size_t)(2 * t + 1) * Kp + k] = du1;
+            const float2 u = L.U[t];
+            const float v0 = u.x + z.x, v1 = u.y + z.y;
+            const float s0 = fminf(fmaxf(v0, p.u_min[0]), p.u_max[0]);
+            const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
+            float f0, f1;
+            Model<MODEL>::inputs(p, s0, s1, f0, f1);
+            L.in[idx] = make_float4(f0, f1, cw0 * u.x * v0 + cw1 * u.y * v1, 0.0f);
+            if (kk < K) {
+                p.du[(size_t)(2 * t) * Kp + kk] = z.x;
+                p.du[(size_t)(2 * t + 1) * Kp + kk] = z.y;
             }
-        } else {
-            const int j = t & (G - 1);
-            if (j == 0) {
-                const int tt = t + g;
-                const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)tt, c_lo, c_hi), p.seed_lo, p.seed_hi);
-                const float2 z = nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
-                my_du0 = z.x;
-                my_du1 = z.y;
-                if (valid && tt < T) {
-                    p.du[(size_t)(2 * tt) * Kp + k] = my_du0;
-                    p.du[(size_t)(2 * tt + 1) * Kp + k] = my_du1;
+        }
+        __syncthreads();
+        // (2) dynamics: one lane per sample; poses to LDS, tracking + control cost
+        if (owner) {
+            float4 nin = L.in[tid];
+            for (int tt = 0; tt < tc; ++tt) {
+                const float4 in = nin;
+                if (tt + 1 < tc) nin = L.in[(tt + 1) * S + tid];
+                const float* rf = L.ref + (t0 + tt + 1) * NS;
+                float ref[NS];
+#pragma unroll
+                for (int a = 0; a < NS; ++a) ref[a] = rf[a];
+                Model<MODEL>::step(p, x, in.x, in.y, sth, cth);
+                heading_sincos(x[2], sth, cth);
+                L.pose[tt * S + tid] = make_float4(x[0], x[1], cth, sth);
+                float q = 0.0f;
+#pragma unroll
+                for (int a = 0; a < NS; ++a) {
+                    const float d = x[a] - ref[a];
+                    q = fmaf(p.Q[a], d * d, q);
                 }
-            }
-            du0 = lane_read(my_du0, gbase + j);
-            du1 = lane_read(my_du1, gbase + j);
-        }
-
-        // -- dynamics with saturated inputs --
-        const float2 u = L.U[t];
-        const float v0 = u.x + du0, v1 = u.y + du1;
-        const float s0 = fminf(fmaxf(v0, p.u_min[0]), p.u_max[0]);
-        const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
-        Model<MODEL>::step(p, x, s0, s1, sth, cth);
-        sincosf(x[2], &sth, &cth);
-
-        // -- shape points and this lane's share of the fused barrier --
-        float px[PM], py[PM];
-#pragma unroll
-        for (int i = 0; i < PM; ++i) {
-            px[i] = x[0] + (sa[i] * cth - sb[i] * sth);
-            py[i] = x[1] + (sa[i] * sth + sb[i] * cth);
-        }
-        float acc = 0.0f;
-        for (int j = g; j < J; j += G) {
-            const float4 o = L.obs[j];
-#pragma unroll
-            for (int i = 0; i < PM; ++i) {
-                if (PT || i < P) {
-                    const float dx = px[i] - o.x, dy = py[i] - o.y;
-                    acc += barrier_rcp(fmaf(dx, dx, fmaf(dy, dy, o.z)), eps);
-                }
+                two_sum_acc(S_hi, S_lo, q + in.z);
             }
         }
-        if (has_map) {
-#pragma unroll
-            for (int i = 0; i < PM; ++i) {
-                if ((PT || i < P) && (i & (G - 1)) == g) {
-                    acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px[i], inv_res, offx),
-                                                  fmaf(py[i], inv_res, offy)),
-                                       eps);
-                }
+        __syncthreads();
+        // (3) fused barrier of every (step, sample), over nsp obstacle ranges
+        for (int u = tid; u < items * nsp; u += kRollBlock) {
+            const int sp = u / items, idx = u - sp * items;
+            const int j0 = sp * J / nsp, j1 = (sp + 1) * J / nsp;
+            bpart[sp * chunk + idx] = fused_barrier_pose<PT>(p, L, P, sa, sb, L.pose[idx], j0, j1,
+                                                             has_map && sp == 0, inv_res, offx, offy);
+        }
+        __syncthreads();
+        // (4) barrier state and its cost
+        if (owner) {
+            for (int tt = 0; tt < tc; ++tt) {
+                float b = bpart[tt * S + tid];
+                for (int sp = 1; sp < nsp; ++sp) b += bpart[sp * chunk + tt * S + tid];
+                beta = fmaf(p.gamma_b, beta, b);
+                two_sum_acc(S_hi, S_lo, p.r_b * beta);
             }
         }
-        const float b = group_sum<G>(acc);
-
-        // -- barrier state (eq. barrier_update, sample-dependent part) and running cost --
-        beta = fmaf(p.gamma_b, beta, b);
-        const float* rf = L.ref + (t + 1) * NS;
-        float q = 0.0f;
-#pragma unroll
-        for (int a = 0; a < NS; ++a) {
-            const float d = x[a] - rf[a];
-            q = fmaf(p.Q[a], d * d, q);
-        }
-        const float ctrl = cw0 * u.x * v0 + cw1 * u.y * v1;
-        two_sum_acc(S_hi, S_lo, q + ctrl + p.r_b * beta);
     }
-    {
+    if (owner) {
         const float* rf = L.ref + T * NS;
         float phi = 0.0f;
 #pragma unroll
@@ -484,13 +610,13 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     }
 
     // ---- tile softmax partials ----
-    if (g == 0 && valid) {
+    if (valid) {
         p.S[k] = S_hi;
         p.S[Kp + k] = S_lo;
     }
     const double Sd = ((double)S_hi + (double)S_lo) + cshift;
     const bool ok = valid && isfinite(Sd);
-    const double rho_b = block_min_d(ok ? Sd : INFINITY, L.slots);
+    const double rho_b = block_min_d<kRollWaves>(ok ? Sd : INFINITY, L.slots);
     const bool any = isfinite(rho_b);
     const bool use64 = any && (p.normaliser == MPPI_NORM_ON ||
                                (p.normaliser == MPPI_NORM_AUTO && fabs(rho_b) >= 1024.0 * (double)p.lambda));
@@ -499,125 +625,133 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         const double d = (Sd - rho_b) / (double)p.lambda;
         ek = use64 ? exp(-d) : (double)expf(-(float)d);
     }
-    if (g == 0) L.e[sidx] = ek;
-    if (g == 0 && valid) p.e[k] = (float)ek;
-    __syncthreads();
-    const int spt = p.spt;
+    if (owner) L.e[tid] = ek;
+    if (valid) p.e[k] = (float)ek;
     double eta_b;
-    if (use64) eta_b = block_sum_d(tid < spt ? L.e[tid] : 0.0, L.slots);
-    else eta_b = (double)block_sum_f(tid < spt ? (float)L.e[tid] : 0.0f, L.slots);
+    if (use64) eta_b = block_sum_d<kRollWaves>(ek, L.slots);
+    else eta_b = (double)block_sum_f<kRollWaves>((float)ek, L.slots);
 
-    // N_b[r] = sum over the tile's samples of e_k du[r][k]; one wave per row.
-    const int wave = tid >> 6;
-    const int k0 = tile * spt;
-    const int nk = min(spt, K - k0);
-    for (int r = wave; r < 2 * T; r += kBlock / kWave) {
-        const float* row = p.du + (size_t)r * Kp + k0;
+    // N_b[r] = sum over the tile's samples of e_k du[r][k]: TPR consecutive
+    // threads share a row, each summing every TPR-th sample in order, then
+    // combining across the TPR threads.
+    const int R = 2 * T;
+    int tpr = 1;
+    while (tpr < 64 && tpr * 2 * R <= kRollBlock) tpr *= 2;
+    const int rows_per_pass = kRollBlock / tpr;
+    const int part = tid & (tpr - 1);
+    const int k0 = tile * S;
+    const int nk = min(S, K - k0);
+    for (int r0 = 0; r0 < R; r0 += rows_per_pass) {
+        const int r = r0 + tid / tpr;
         double out;
         if (use64) {
             double a = 0.0;
-            for (int s = lane; s < nk; s += kWave) a += L.e[s] * (double)row[s];
-            out = wave_sum_d(a);
+            if (r < R) {
+                const float* row = p.du + (size_t)r * Kp + k0;
+                for (int s = part; s < nk; s += tpr) a += L.e[s] * (double)row[s];
+            }
+            for (int m = 1; m < tpr; m <<= 1) a += __shfl_xor(a, m);
+            out = a;
         } else {
             float a = 0.0f;
-            for (int s = lane; s < nk; s += kWave) a = fmaf((float)L.e[s], row[s], a);
-            out = (double)wave_sum_f(a);
+            if (r < R) {
+                const float* row = p.du + (size_t)r * Kp + k0;
+                for (int s = part; s < nk; s += tpr) a = fmaf((float)L.e[s], row[s], a);
+            }
+            for (int m = 1; m < tpr; m <<= 1) a += __shfl_xor(a, m);
+            out = (double)a;
         }
-        if (lane == 0) p.partN[(size_t)r * p.tiles + tile] = any ? out : 0.0;
+        if (part == 0 && r < R) p.partN[(size_t)r * p.tiles + tile] = any ? out : 0.0;
     }
     if (tid == 0) {
         p.rho_b[tile] = rho_b;
         p.eta_b[tile] = any ? eta_b : 0.0;
         p.flag_b[tile] = use64 ? 1 : 0;
-    }
-
-    // ---- completion ticket; the last tile merges the tile scalars ----
-    __threadfence();
-    __syncthreads();
-    __shared__ uint32_t s_last;
-    if (tid == 0) s_last = atomicAdd(&p.st->tiles_done, 1u) == (uint32_t)(p.tiles - 1) ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-
-    const int nt = p.tiles;
-    double m = INFINITY;
-    for (int b = tid; b < nt; b += kBlock) m = fmin(m, __builtin_nontemporal_load(&p.rho_b[b]));
-    const double rho = block_min_d(m, L.slots);
-    double es = 0.0;
-    int n64 = 0;
-    if (isfinite(rho)) {
-        for (int b = tid; b < nt; b += kBlock) {
-            const double rb = __builtin_nontemporal_load(&p.rho_b[b]);
-            const double f = isfinite(rb) ? exp(-(rb - rho) / (double)p.lambda) : 0.0;
-            p.f_b[b] = f;
-            es += f * __builtin_nontemporal_load(&p.eta_b[b]);
-            n64 += __builtin_nontemporal_load(&p.flag_b[b]);
+        if (tile == 0) {
+            // identical in every tile; the update kernel reports them
+            CtrlState* st = p.st;
+            st->beta0 = beta0;
+            st->beta_d = beta_d;
+            st->cshift = cshift;
         }
-    }
-    const double eta = block_sum_d(es, L.slots);
-    const double n64s = block_sum_d((double)n64, L.slots);
-    if (tid == 0) {
-        CtrlState* st = p.st;
-        st->rho = rho;
-        st->eta = eta;
-        st->status = (isfinite(rho) && eta > 0.0 && isfinite(eta)) ? MPPI_OK : MPPI_E_NUMERIC;
-        st->beta0 = beta0;
-        st->beta_d = beta_d;
-        st->cshift = cshift;
-        st->fp64_tiles = (int32_t)n64s;
-        st->tiles_done = 0u;
-        st->iter = iter + 1u;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Update rows [row0, row0 + 4) of one controller (one wave per row).
+// Update of control rows [row0, row0 + 4) of one controller, one wave per row.
+// Every workgroup first merges the tile minima and normalisers itself
+// (eq. control_update: rho = min_b rho_b, f_b = exp(-(rho_b - rho)/lambda),
+// eta = sum_b f_b eta_b), then U*[t][c] = U[t][c] + sum_b f_b N_b[t][c] / eta,
+// coalesced over tiles; it writes U*, the shifted warm start (Alg. 1 closing
+// loop) into the other half of the double buffer and u0*; the workgroup of
+// row 0 also records the iteration in the controller's state.
 // ---------------------------------------------------------------------------
-__device__ void update_rows(const DevParams& p, int row0, float* u0_dev)
+__device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, double* sf, double* slots)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int r = row0 + (threadIdx.x >> 6);
-    const int T = p.T;
-    const CtrlState* st = p.st;
-    const uint32_t iter = st->iter;                 // already advanced by the rollout
-    const float* Uin = p.U + (size_t)((iter - 1u) & 1u) * T * kM;
-    float* Uout = p.U + (size_t)(iter & 1u) * T * kM;
-    const bool ok = st->status == MPPI_OK;
-    if (r >= 2 * T) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    const int T = p.T, nt = p.tiles;
+    CtrlState* st = p.st;
+    const float* Uin = p.U + (size_t)(parity & 1u) * T * kM;
+    float* Uout = p.U + (size_t)((parity + 1u) & 1u) * T * kM;
+    const bool first = row0 == 0;
 
-    float us;
-    if (ok) {
-        const int nt = p.tiles;
-        const double* row = p.partN + (size_t)r * nt;
-        double a = 0.0;
-        for (int b = lane; b < nt; b += kWave) a += p.f_b[b] * row[b];
-        a = wave_sum_d(a);
-        us = (float)((double)Uin[r] + a / st->eta);
-    } else {
-        us = Uin[r];
+    double m = INFINITY;
+    for (int b = tid; b < nt; b += kUpdBlock) m = fmin(m, p.rho_b[b]);
+    const double rho = block_min_d<kUpdWaves>(m, slots);
+    double es = 0.0, n64 = 0.0;
+    for (int b = tid; b < nt; b += kUpdBlock) {
+        const double rb = p.rho_b[b];
+        const double f = (isfinite(rho) && isfinite(rb)) ? exp(-(rb - rho) / (double)p.lambda) : 0.0;
+        sf[b] = f;
+        if (first) p.f_b[b] = f;
+        es += f * p.eta_b[b];
+        n64 += (double)p.flag_b[b];
     }
-    if (lane != 0) return;
-    p.Ustar[r] = us;
-    const int t = r >> 1;
-    if (ok) {
-        if (t >= 1) Uout[r - 2] = us;
-        if (t == T - 1) Uout[r] = p.init_mode == MPPI_INIT_ZERO ? 0.0f : us;
-    } else {
-        Uout[r] = us;
-    }
-    if (t == 0) {
-        if (u0_dev) u0_dev[r] = us;
-        if (p.res) p.res->u0[r] = us;
-        if (r == 0) {
-            CtrlState* sw = p.st;
-            const uint64_t c = sw->counter;
-            sw->last_counter = c;
-            if (ok) sw->counter = c + 1u;
-            if (p.res) {
-                p.res->status = st->status;
-                p.res->counter = c;
+    const double eta = block_sum_d<kUpdWaves>(es, slots);      // also publishes sf to the block
+    const double n64s = block_sum_d<kUpdWaves>(n64, slots);
+    const bool ok = isfinite(rho) && isfinite(eta) && eta > 0.0;
+
+    const int r = row0 + wave;
+    if (r < 2 * T) {
+        float us;
+        if (ok) {
+            const double* row = p.partN + (size_t)r * nt;
+            double a = 0.0;
+            for (int b = lane; b < nt; b += kWave) a += sf[b] * row[b];
+            a = wave_sum_d(a);
+            us = (float)((double)Uin[r] + a / eta);
+        } else {
+            us = Uin[r];
+        }
+        if (lane == 0) {
+            p.Ustar[r] = us;
+            const int t = r >> 1;
+            if (ok) {
+                if (t >= 1) Uout[r - 2] = us;
+                if (t == T - 1) Uout[r] = p.init_mode == MPPI_INIT_ZERO ? 0.0f : us;
+            } else {
+                Uout[r] = us;
             }
+            if (t == 0) {
+                if (u0_dev) u0_dev[r] = us;
+                if (p.res) p.res->u0[r] = us;
+            }
+        }
+    }
+    if (first && tid == 0) {
+        const uint64_t c = st->counter;
+        const int status = ok ? MPPI_OK : MPPI_E_NUMERIC;
+        st->last_counter = c;
+        if (ok) st->counter = c + 1u;
+        st->rho = rho;
+        st->eta = eta;
+        st->status = status;
+        st->fp64_tiles = (int32_t)n64s;
+        st->iter += 1u;
+        if (p.res) {
+            p.res->status = status;
+            p.res->counter = c;
         }
     }
 }
@@ -625,47 +759,50 @@ __device__ void update_rows(const DevParams& p, int row0, float* u0_dev)
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <int MODEL, int G, int PT>
-__global__ __launch_bounds__(kBlock) void k_rollout(DevParams p, StepArgs a)
+template <int MODEL, int S, int PT>
+__global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     X0 xs;
 #pragma unroll
     for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0_ptr ? (i < p.n ? a.x0_ptr[i] : 0.0f) : a.x0[i];
-    rollout_tile<MODEL, G, PT>(p, blockIdx.x, xs, smem);
+    xs.parity = a.parity;
+    rollout_tile<MODEL, S, PT>(p, blockIdx.x, xs, smem);
 }
 
-__global__ __launch_bounds__(kBlock) void k_update(DevParams p, StepArgs a)
+__global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
 {
-    update_rows(p, blockIdx.x * kRowsPerBlock, a.u0_dev);
+    __shared__ double sf[kMaxTiles];
+    __shared__ double slots[kUpdWaves];
+    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, sf, slots);
 }
 
-template <int MODEL, int G>
+template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD) rollout_tile<MODEL, G, PD>(p, tile, xs, smem);
-    else rollout_tile<MODEL, G, 0>(p, tile, xs, smem);
+    if (p.P == PD) rollout_tile<MODEL, S, PD>(p, tile, xs, smem);
+    else rollout_tile<MODEL, S, 0>(p, tile, xs, smem);
 }
 
 template <int MODEL>
-__device__ __forceinline__ void dispatch_g(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
+__device__ __forceinline__ void dispatch_s(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
-    switch (p.G) {
-    case 1: dispatch_p<MODEL, 1>(p, tile, xs, smem); break;
-    case 2: dispatch_p<MODEL, 2>(p, tile, xs, smem); break;
-    case 4: dispatch_p<MODEL, 4>(p, tile, xs, smem); break;
-    case 8: dispatch_p<MODEL, 8>(p, tile, xs, smem); break;
-    default: dispatch_p<MODEL, 16>(p, tile, xs, smem); break;
+    switch (p.spt) {
+    case 16: dispatch_p<MODEL, 16>(p, tile, xs, smem); break;
+    case 32: dispatch_p<MODEL, 32>(p, tile, xs, smem); break;
+    case 64: dispatch_p<MODEL, 64>(p, tile, xs, smem); break;
+    case 128: dispatch_p<MODEL, 128>(p, tile, xs, smem); break;
+    default: dispatch_p<MODEL, 256>(p, tile, xs, smem); break;
     }
 }
 
 // Persistent rollout over a work list of (controller, tile) units, taken in
 // list order (the host sorts it longest-first).  Every block leaves the loop
 // once the list is exhausted; the last block to leave resets the queue.
-__global__ __launch_bounds__(kBlock) void k_batch_rollout(const DevParams* __restrict__ ps,
-                                                          const BatchUnit* __restrict__ units, int nunits,
-                                                          const float* __restrict__ x0s, uint32_t* queue)
+__global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* __restrict__ ps,
+                                                              const BatchUnit* __restrict__ units, int nunits,
+                                                              const BatchIn* __restrict__ in, uint32_t* queue)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_unit;
@@ -679,11 +816,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_rollout(const DevParams* __res
         const DevParams& p = ps[bu.ctrl];
         X0 xs;
 #pragma unroll
-        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = x0s[(size_t)bu.ctrl * (MPPI_NMAX + 2) + i];
+        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
+        xs.parity = in[bu.ctrl].parity;
         switch (p.model) {
-        case MPPI_QUAD6: dispatch_g<MPPI_QUAD6>(p, bu.tile, xs, smem); break;
-        case MPPI_QUAD5: dispatch_g<MPPI_QUAD5>(p, bu.tile, xs, smem); break;
-        default: dispatch_g<MPPI_CAR>(p, bu.tile, xs, smem); break;
+        case MPPI_QUAD6: dispatch_s<MPPI_QUAD6>(p, bu.tile, xs, smem); break;
+        case MPPI_QUAD5: dispatch_s<MPPI_QUAD5>(p, bu.tile, xs, smem); break;
+        default: dispatch_s<MPPI_CAR>(p, bu.tile, xs, smem); break;
         }
         __syncthreads();
     }
@@ -696,25 +834,29 @@ __global__ __launch_bounds__(kBlock) void k_batch_rollout(const DevParams* __res
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_update(const DevParams* __restrict__ ps,
-                                                         const RowUnit* __restrict__ units, float* u0s)
+// One workgroup per (controller, four control rows) of the batch.
+__global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __restrict__ ps,
+                                                            const RowUnit* __restrict__ units,
+                                                            const BatchIn* __restrict__ in, float* u0s)
 {
+    __shared__ double sf[kMaxTiles];
+    __shared__ double slots[kUpdWaves];
     const RowUnit ru = units[blockIdx.x];
-    update_rows(ps[ru.ctrl], ru.row0, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr);
+    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, sf, slots);
 }
 
 // w_k = e_k f_b(k) / eta: the weights the update used.
-__global__ __launch_bounds__(kBlock) void k_weights(DevParams p, double* w)
+__global__ __launch_bounds__(256) void k_weights(DevParams p, double* w)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
+    const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= p.K) return;
     const CtrlState* st = p.st;
     w[k] = st->status == MPPI_OK ? (double)p.e[k] * p.f_b[k / p.spt] / st->eta : 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_philox_words(DevParams p, uint64_t counter, uint32_t* out)
+__global__ __launch_bounds__(256) void k_philox_words(DevParams p, uint64_t counter, uint32_t* out)
 {
-    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= p.K * p.T) return;
     const int k = idx / p.T, t = idx - k * p.T;
     const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)t, (uint32_t)counter, (uint32_t)(counter >> 32)),
@@ -723,35 +865,35 @@ __global__ __launch_bounds__(kBlock) void k_philox_words(DevParams p, uint64_t c
     *o = r;
 }
 
-template <int MODEL, int G>
-hipError_t launch_rollout_mg(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
+template <int MODEL, int S>
+hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD) hipLaunchKernelGGL((k_rollout<MODEL, G, PD>), dim3(p.tiles), dim3(kBlock), lds, s, p, a);
-    else hipLaunchKernelGGL((k_rollout<MODEL, G, 0>), dim3(p.tiles), dim3(kBlock), lds, s, p, a);
+    if (p.P == PD) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    else hipLaunchKernelGGL((k_rollout<MODEL, S, 0>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     return hipGetLastError();
 }
 
 template <int MODEL>
 hipError_t launch_rollout_m(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
-    switch (p.G) {
-    case 1: return launch_rollout_mg<MODEL, 1>(p, a, lds, s);
-    case 2: return launch_rollout_mg<MODEL, 2>(p, a, lds, s);
-    case 4: return launch_rollout_mg<MODEL, 4>(p, a, lds, s);
-    case 8: return launch_rollout_mg<MODEL, 8>(p, a, lds, s);
-    case 16: return launch_rollout_mg<MODEL, 16>(p, a, lds, s);
+    switch (p.spt) {
+    case 16: return launch_rollout_ms<MODEL, 16>(p, a, lds, s);
+    case 32: return launch_rollout_ms<MODEL, 32>(p, a, lds, s);
+    case 64: return launch_rollout_ms<MODEL, 64>(p, a, lds, s);
+    case 128: return launch_rollout_ms<MODEL, 128>(p, a, lds, s);
+    case 256: return launch_rollout_ms<MODEL, 256>(p, a, lds, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-bool tile_lanes_supported(int G) { return G == 1 || G == 2 || G == 4 || G == 8 || G == 16; }
+bool tile_samples_supported(int S) { return S >= 16 && S <= kMaxTile && (S & (S - 1)) == 0; }
 
 hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s)
 {
-    const size_t lds = tile_lds_bytes(p.J, p.T, p.n);
+    const size_t lds = tile_lds_bytes(p.J, p.T, p.n, p.spt);
     switch (p.model) {
     case MPPI_QUAD6: return launch_rollout_m<MPPI_QUAD6>(p, a, lds, s);
     case MPPI_QUAD5: return launch_rollout_m<MPPI_QUAD5>(p, a, lds, s);
@@ -762,42 +904,42 @@ hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s)
 
 hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s)
 {
-    const int rows = 2 * p.T;
-    hipLaunchKernelGGL(k_update, dim3((rows + kRowsPerBlock - 1) / kRowsPerBlock), dim3(kBlock), 0, s, p, a);
+    hipLaunchKernelGGL(k_update, dim3((2 * p.T + kUpdWaves - 1) / kUpdWaves), dim3(kUpdBlock), 0, s, p, a);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_rollout(const DevParams* d_params, const BatchUnit* d_units, int nunits,
-                                const float* d_x0s, uint32_t* d_queue, int grid, size_t lds, hipStream_t s)
+                                const BatchIn* d_in, uint32_t* d_queue, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_rollout, dim3(grid), dim3(kBlock), lds, s, d_params, d_units, nunits, d_x0s, d_queue);
+    hipLaunchKernelGGL(k_batch_rollout, dim3(grid), dim3(kRollBlock), lds, s, d_params, d_units, nunits, d_in,
+                       d_queue);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, float* d_u0s,
-                               hipStream_t s)
+hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, const BatchIn* d_in,
+                               float* d_u0s, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_update, dim3(nunits), dim3(kBlock), 0, s, d_params, d_units, d_u0s);
+    hipLaunchKernelGGL(k_batch_update, dim3(nunits), dim3(kUpdBlock), 0, s, d_params, d_units, d_in, d_u0s);
     return hipGetLastError();
 }
 
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_weights, dim3((p.K + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, d_w);
+    hipLaunchKernelGGL(k_weights, dim3((p.K + 255) / 256), dim3(256), 0, s, p, d_w);
     return hipGetLastError();
 }
 
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s)
 {
     const int n = p.K * p.T;
-    hipLaunchKernelGGL(k_philox_words, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, counter, d_words);
+    hipLaunchKernelGGL(k_philox_words, dim3((n + 255) / 256), dim3(256), 0, s, p, counter, d_words);
     return hipGetLastError();
 }
 
 int batch_rollout_blocks_per_cu(size_t lds)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_rollout, kBlock, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_rollout, kRollBlock, lds) != hipSuccess) return 1;
     return blocks > 0 ? blocks : 1;
 }
 

@@ -93,7 +93,7 @@ extern "C" int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_con
     c->seed = 0;
     c->normaliser = MPPI_NORM_AUTO;
     c->init_mode = MPPI_INIT_REPEAT;
-    c->tile_lanes = 0;
+    c->tile_samples = 0;
     const int n = state_dim(model);
     for (int a = 0; a < n; ++a) c->Q[a] = a < 2 ? 1.0f : 0.1f;
     for (int a = 0; a < n; ++a) c->Qf[a] = 10.0f * c->Q[a];
@@ -159,7 +159,9 @@ std::string validate_config(const mppi_config* c)
     if (c->model == MPPI_CAR && !(c->wheelbase > 0)) return "wheelbase must be > 0";
     if (c->normaliser < MPPI_NORM_AUTO || c->normaliser > MPPI_NORM_OFF) return "unknown normaliser mode";
     if (c->init_mode != MPPI_INIT_REPEAT && c->init_mode != MPPI_INIT_ZERO) return "unknown init mode";
-    if (c->tile_lanes != 0 && !tile_lanes_supported(c->tile_lanes)) return "tile_lanes must be 0, 1, 2, 4, 8 or 16";
+    if (c->tile_samples != 0 && !tile_samples_supported(c->tile_samples))
+        return "tile_samples must be 0, 16, 32, 64, 128 or 256";
+    if (!(c->h_eps >= 1e-9f && c->h_eps <= 1e6f)) return "h_eps must lie in [1e-9, 1e6]";
     for (int i = 0; i < 7; ++i)
         if (c->reserved[i] != 0) return "reserved fields must be zero";
     return "";
@@ -221,24 +223,28 @@ int mppi_ctrl::write_state_field(size_t offset, const void* src, size_t bytes)
 
 namespace dbas {
 
-// Lanes per sample: enough groups to give every SIMD of the chip at least a
-// couple of waves, but keep at least a few obstacles per lane.  Used when the
-// configuration leaves tile_lanes at 0 and no measured choice is cached.
-int heuristic_tile_lanes(int K, int J)
+// Samples per tile: the largest tile (at most 64) that still gives every CU of
+// the chip a tile, and whose chunk fits the LDS budget.  Used when the
+// configuration leaves tile_samples at 0 and no measured choice is cached.
+int heuristic_tile_samples(int K, int J, int T, int n)
 {
-    const long target_lanes = 131072;   // 256 CUs x 4 SIMDs x 2 waves x 64 lanes
-    int G = 1;
-    while (G < 16 && (long)K * G < target_lanes && J / (2 * G) >= 4) G *= 2;
-    return G;
+    int S = 16;
+    while (S < 64 && (long)K / (2 * S) >= 256) S *= 2;
+    while (S > 16 && tile_chunk_slots(J, T, n, S) == 0) S /= 2;
+    while (S < kMaxTile && (K + S - 1) / S > kMaxTiles) S *= 2;
+    return S;
 }
 
 }  // namespace dbas
 
-int mppi_ctrl::configure_tiles(int G)
+int mppi_ctrl::configure_tiles(int S)
 {
-    p.G = G;
-    p.spt = kBlock / G;
-    p.tiles = (cfg.K + p.spt - 1) / p.spt;
+    if (!tile_samples_supported(S) || tile_chunk_slots(p.J, cfg.T, p.n, S) == 0)
+        return fail(MPPI_E_INVALID, "J=%d obstacles with T=%d do not fit the rollout's LDS budget at %d samples per tile",
+                    p.J, cfg.T, S);
+    p.spt = S;
+    p.tiles = (cfg.K + S - 1) / S;
+    if (p.tiles > kMaxTiles) return fail(MPPI_E_INVALID, "K=%d needs more than %d tiles of %d samples", cfg.K, kMaxTiles, S);
     return MPPI_OK;
 }
 
@@ -326,8 +332,13 @@ extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 
-    h->configure_tiles(cfg->tile_lanes ? cfg->tile_lanes : heuristic_tile_lanes(K, 0));
-    h->tiles_fixed = cfg->tile_lanes != 0;
+    st = h->configure_tiles(cfg->tile_samples ? cfg->tile_samples : heuristic_tile_samples(K, 0, T, n));
+    if (st) {
+        set_global_error("mppi_create: " + h->err);
+        delete h;
+        return st;
+    }
+    h->tiles_fixed = cfg->tile_samples != 0;
 
     p.U = static_cast<float*>(h->dalloc(sizeof(float) * 2 * T * kM, &st));
     p.Ustar = static_cast<float*>(h->dalloc(sizeof(float) * T * kM, &st));
@@ -383,8 +394,9 @@ extern "C" void mppi_destroy(mppi_t* h) { delete h; }
 int mppi_ctrl::retile()
 {
     if (tiles_fixed) return MPPI_OK;
-    const int G = choose_tile_lanes(this);
-    if (G == p.G) return MPPI_OK;
+    const int S = choose_tile_samples(this);
+    if (S == p.spt) return MPPI_OK;
+    if (tile_chunk_slots(p.J, cfg.T, p.n, S) == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
     int s = sync();
     if (s) return s;
     for (double* ptr : {p.rho_b, p.eta_b, p.f_b}) {
@@ -395,7 +407,7 @@ int mppi_ctrl::retile()
     (void)hipFree(p.flag_b);
     allocations.erase(std::find(allocations.begin(), allocations.end(), (void*)p.partN));
     (void)hipFree(p.partN);
-    configure_tiles(G);
+    configure_tiles(S);
     ++version;
     return alloc_tile_buffers();
 }
@@ -405,6 +417,8 @@ extern "C" int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int3
     CHECK_HANDLE(h);
     if (J < 0 || J > MPPI_JMAX) return h->fail(MPPI_E_INVALID, "J=%d outside 0..%d", J, MPPI_JMAX);
     if (J > 0 && !cxcyr) return h->fail(MPPI_E_INVALID, "obstacles pointer is NULL");
+    if (tile_chunk_slots(J, h->cfg.T, h->p.n, h->tiles_fixed ? h->p.spt : 16) == 0)
+        return h->fail(MPPI_E_INVALID, "J=%d obstacles with T=%d exceed the rollout's LDS budget", J, h->cfg.T);
     std::vector<float> tmp;
     if (J > 0 && mem == MPPI_MEM_HOST) {
         if (!finite_all(cxcyr, (size_t)3 * J)) return h->fail(MPPI_E_INVALID, "non-finite obstacle");
@@ -492,7 +506,7 @@ extern "C" int mppi_set_controls(mppi_t* h, const float* U, int32_t mem)
     CtrlState st;
     int s = h->read_state(&st);
     if (s) return s;
-    HIP_TRY(h, hipMemcpy(h->p.U + (size_t)(st.iter & 1u) * cnt, U, sizeof(float) * cnt,
+    HIP_TRY(h, hipMemcpy(h->p.U + (size_t)(h->iter & 1u) * cnt, U, sizeof(float) * cnt,
                          mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
     return MPPI_OK;
 }
@@ -504,6 +518,7 @@ int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_
     if (x0_host) std::memcpy(a.x0, x0_host, sizeof(float) * p.n);
     a.x0_ptr = x0_dev;
     a.u0_dev = u0_dev;
+    a.parity = iter & 1u;
     HIP_TRY(this, hipSetDevice(device));
     hipEvent_t* ev = nullptr;
     if (profiling) {
@@ -514,6 +529,7 @@ int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_
     HIP_TRY(this, launch_rollout(p, a, stream));
     if (ev) HIP_TRY(this, hipEventRecord(ev[1], stream));
     HIP_TRY(this, launch_update(p, a, stream));
+    ++iter;
     if (ev) HIP_TRY(this, hipEventRecord(ev[2], stream));
     return MPPI_OK;
 }
@@ -582,7 +598,7 @@ extern "C" int mppi_synchronize(mppi_t* h)
     if (s) return s;
     CtrlState st;
     HIP_TRY(h, hipMemcpy(&st, h->p.st, sizeof st, hipMemcpyDeviceToHost));
-    return st.iter == 0 ? MPPI_OK : st.status;
+    return h->iter == 0 ? MPPI_OK : st.status;
 }
 
 extern "C" int mppi_get_controls(mppi_t* h, float* U)
@@ -593,7 +609,7 @@ extern "C" int mppi_get_controls(mppi_t* h, float* U)
     int s = h->read_state(&st);
     if (s) return s;
     const size_t cnt = (size_t)h->cfg.T * kM;
-    HIP_TRY(h, hipMemcpy(U, h->p.U + (size_t)(st.iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(U, h->p.U + (size_t)(h->iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
     return MPPI_OK;
 }
 
@@ -659,13 +675,13 @@ extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
     int s = h->read_state(&st);
     if (s) return s;
     info->counter = st.last_counter;
-    info->status = st.iter == 0 ? MPPI_OK : st.status;
+    info->status = h->iter == 0 ? MPPI_OK : st.status;
     info->fp64_tiles = st.fp64_tiles;
     info->rho = st.rho;
     info->eta = st.eta;
     info->beta0 = st.beta0;
     info->beta_d = st.beta_d;
-    info->tile_lanes = h->p.G;
+    info->tile_samples = h->p.spt;
     info->tiles = h->p.tiles;
     return MPPI_OK;
 }
@@ -696,7 +712,7 @@ extern "C" int mppi_get_state(mppi_t* h, mppi_state* out)
     out->counter = st.counter;
     out->S_e = st.S_e;
     const size_t cnt = (size_t)h->cfg.T * kM;
-    HIP_TRY(h, hipMemcpy(out->U, h->p.U + (size_t)(st.iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(out->U, h->p.U + (size_t)(h->iter & 1u) * cnt, sizeof(float) * cnt, hipMemcpyDeviceToHost));
     return MPPI_OK;
 }
 

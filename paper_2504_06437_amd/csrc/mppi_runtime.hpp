@@ -16,6 +16,7 @@ struct mppi_ctrl {
     bool poisoned = false;
     bool tiles_fixed = false;
     uint64_t version = 0;            // bumps whenever DevParams change (batches re-upload)
+    uint32_t iter = 0;               // iterations launched; U[iter & 1] holds the warm start
     std::string err;
     dbas::DevParams p{};
     std::vector<void*> allocations;
@@ -37,7 +38,7 @@ struct mppi_ctrl {
     int sync();
     int read_state(dbas::CtrlState* out);
     int write_state_field(size_t offset, const void* src, size_t bytes);
-    int configure_tiles(int G);
+    int configure_tiles(int S);
     int alloc_tile_buffers();
     int retile();
     int launch_step(const float* x0_host, const float* x0_dev, float* u0_dev);
@@ -45,9 +46,9 @@ struct mppi_ctrl {
 
 namespace dbas {
 std::string validate_config(const mppi_config* c);
-int heuristic_tile_lanes(int K, int J);
+int heuristic_tile_samples(int K, int J, int T, int n);
 // Autotuned lanes-per-sample for this controller's (model, K, T, J, P).
-int choose_tile_lanes(mppi_ctrl* h);
+int choose_tile_samples(mppi_ctrl* h);
 }  // namespace dbas
 
 void set_global_error(const std::string& s);

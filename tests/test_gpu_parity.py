@@ -133,10 +133,16 @@ def test_iteration_matches_oracle(name, make):
     _one_iteration(make())
 
 
-@pytest.mark.parametrize("G", [1, 2, 4, 8, 16])
-def test_every_tile_shape_matches_oracle(G):
-    _one_iteration(W.quad_small(K=300, T=11, J=13), tile_lanes=G)
-    _one_iteration(W.car(K=200, T=9, J=21), tile_lanes=G)
+@pytest.mark.parametrize("S", [16, 32, 64, 128, 256])
+def test_every_tile_shape_matches_oracle(S):
+    _one_iteration(W.quad_small(K=300, T=11, J=13), tile_samples=S)
+    _one_iteration(W.car(K=200, T=9, J=21), tile_samples=S)
+
+
+def test_long_horizon_spans_several_chunks():
+    """T = 300 with 256-sample tiles needs several horizon chunks."""
+    _one_iteration(W.car(K=600, T=300, J=20), tile_samples=256)
+    _one_iteration(W.quad_small(K=100, T=200, J=12), tile_samples=16)
 
 
 def test_exploration_rate_scales_noise_and_control_cost():
@@ -291,7 +297,7 @@ def test_invalid_inputs_are_rejected_before_launch():
         c.set_exploration(-1.0)
     with pytest.raises(A.MppiError):
         c.set_obstacles(np.array([[1.0, 2.0, -0.5]]))
-    for bad in ({"lambda": 0.0}, {"gamma_b": 1.0}, {"K": 0}, {"h_eps": 0.0}, {"tile_lanes": 3}):
+    for bad in ({"lambda": 0.0}, {"gamma_b": 1.0}, {"K": 0}, {"h_eps": 0.0}, {"tile_samples": 3}):
         p = dict(wl["params"])
         p.update(bad)
         with pytest.raises(A.MppiError):
