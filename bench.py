@@ -196,6 +196,70 @@ def load_traffic(kernel: str, workload: str):
     return r.get("bytes_per_launch")
 
 
+def copy_calibration(mib: int, copies: int = 5):
+    """Plain device-to-device copies of known size, run under rocprofv3 --pmc
+    to calibrate FETCH_SIZE / WRITE_SIZE against true bytes."""
+    from paper_2504_06437_amd import hip
+    n = mib * (1 << 20) // 4
+    a, b = hip.DeviceArray((n,)), hip.DeviceArray((n,))
+    for _ in range(copies):
+        hip.copy_device(b, a)
+    hip.synchronize()
+    return {"copy_bytes": a.nbytes, "copies": copies}
+
+
+def _pmc_mean(csv_dir: str, counter: str, kernel_substr: str):
+    """Mean over dispatches of `counter` (summed over its instances) for the
+    kernels whose name contains `kernel_substr`; (mean, dispatches, names)."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Kernel_Name", "")
+                if row.get("Counter_Name") != counter or kernel_substr not in name:
+                    continue
+                key = (name, f, row["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for kernels matching {kernel_substr!r} under {csv_dir}")
+    # the most dispatched instantiation (autotune candidates run only a few times)
+    counts = {}
+    for name, _, _ in per:
+        counts[name] = counts.get(name, 0) + 1
+    top = max(counts, key=counts.get)
+    vals = [v for (name, _, _), v in per.items() if name == top]
+    return sum(vals) / len(vals), len(vals), [top]
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, workload, out_path):
+    """HBM bytes per rollout launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by true bytes / counter reading of a plain copy."""
+    import hashlib
+    cf, _, cnames = _pmc_mean(copy_fetch_dir, "FETCH_SIZE", "copy")
+    cw, _, _ = _pmc_mean(copy_write_dir, "WRITE_SIZE", "copy")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    fk, nf, names = _pmc_mean(fetch_dir, "FETCH_SIZE", "k_rollout")
+    wk, nw, _ = _pmc_mean(write_dir, "WRITE_SIZE", "k_rollout")
+    src = os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    fetch_b, write_b = fk * 1024.0 * f_scale, wk * 1024.0 * w_scale
+    rec = {}
+    if os.path.exists(out_path):
+        rec = json.load(open(out_path))
+    rec.setdefault("rollout", {})[workload] = {
+        "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b, "write_bytes": write_b,
+        "fetch_kib_raw": fk, "write_kib_raw": wk, "dispatches": [nf, nw], "kernels": names,
+        "copy_kernel": cnames, "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+        "kernel_source_sha256_16": digest,
+    }
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec["rollout"][workload]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +267,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 --pmc output folders -> profiles/traffic.json (no GPU use)")
+    ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     args = ap.parse_args()
+    if args.summarize_traffic:
+        wl = W.car()
+        p = wl["params"]
+        workload = f"ground vehicle K={p['K']} T={p['T']} J={len(wl['obstacles'])} P={len(p['shape'])}"
+        r = summarize_traffic(*args.summarize_traffic, args.copy_bytes, workload,
+                              os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps(r, indent=1))
+        return
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(args.copy_calibration)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
               "is described but not built.", file=sys.stderr)

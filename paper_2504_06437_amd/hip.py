@@ -12,7 +12,7 @@ import numpy as np
 
 from . import _lib as A
 
-_H2D, _D2H = 1, 2
+_H2D, _D2H, _D2D = 1, 2, 3
 _hip = None
 
 
@@ -43,6 +43,12 @@ def _ok(e: int, what: str):
 
 def synchronize():
     _ok(runtime().hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+
+def copy_device(dst: "DeviceArray", src: "DeviceArray"):
+    """Device-to-device copy of a whole array (the runtime's blit kernel)."""
+    assert dst.nbytes == src.nbytes
+    _ok(runtime().hipMemcpy(ctypes.c_void_p(dst.ptr), ctypes.c_void_p(src.ptr), src.nbytes, _D2D), "hipMemcpy D2D")
 
 
 class DeviceArray:
