@@ -1,7 +1,7 @@
 """Python handles over the C ABI: Controller (one MPPI controller), Batch
 (many controllers in one persistent graph launch) and Server (continuous
-batching).  Marshalling only; torch supplies device memory and streams where
-a caller wants to pass device buffers."""
+batching).  Marshalling only; device buffers for the device-pointer calls come
+from `hip.DeviceArray`."""
 from __future__ import annotations
 
 import ctypes
@@ -248,3 +248,105 @@ class Batch:
         if st not in (A.OK, A.E_NUMERIC):
             raise A.MppiError(st, "mppi_batch_step: " + self.L.mppi_batch_last_error(self.b).decode())
         return u0s, np.array(list(sts), dtype=np.int32)
+
+
+class Server:
+    """Continuous-batching server: robots with resident state, requests
+    admitted by launch slots and a device-memory budget for sample scratch."""
+
+    def __init__(self, budget_bytes: int = 256 << 20, max_slots: int = 256, streams: int = 2,
+                 max_batch: int = 64, device: int = 0):
+        self.L = A.load()
+        cfg = A.ServerConfig()
+        cfg.abi_version = A.ABI_VERSION
+        cfg.device = device
+        cfg.budget_bytes = int(budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.streams = int(streams)
+        cfg.max_batch = int(max_batch)
+        s = ctypes.c_void_p()
+        st = self.L.mppi_server_create(ctypes.byref(cfg), ctypes.byref(s))
+        if st != A.OK:
+            raise A.MppiError(st, "mppi_server_create: " + (self.L.mppi_server_last_error(None) or b"").decode())
+        self.s = s
+        self.dims = []
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.L.mppi_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st, what):
+        raise A.MppiError(st, f"{what}: " + self.L.mppi_server_last_error(self.s).decode())
+
+    def add_robot(self, params: dict, obstacles) -> int:
+        cfg = make_config(params)
+        obs = _f32(obstacles).reshape(-1, 3)
+        rid = ctypes.c_int32()
+        st = self.L.mppi_server_add_robot(self.s, ctypes.byref(cfg), obs.shape[0],
+                                          obs.ctypes.data if obs.shape[0] else None, ctypes.byref(rid))
+        if st != A.OK:
+            self._err(st, "mppi_server_add_robot")
+        self.dims.append((A.STATE_DIM[params["model"]], int(params["T"])))
+        return rid.value
+
+    def now(self) -> float:
+        return self.L.mppi_server_now(self.s)
+
+    def submit(self, rid: int, x0, x_ref=None, t_arrival: float | None = None) -> int:
+        # an unknown id goes through to the library, which rejects it
+        n, T = self.dims[rid] if 0 <= rid < len(self.dims) else (A.NMAX, 0)
+        x = _f32(x0).reshape(-1)
+        assert x.size >= n
+        ref = None
+        if x_ref is not None:
+            ref = _f32(x_ref).reshape(T + 1, n)
+        tk = ctypes.c_int64()
+        st = self.L.mppi_server_submit(self.s, rid, _fp(x), _fp(ref) if ref is not None else None,
+                                       self.now() if t_arrival is None else float(t_arrival), ctypes.byref(tk))
+        if st != A.OK:
+            self._err(st, "mppi_server_submit")
+        return tk.value
+
+    def poll(self, ticket: int):
+        """(u0, latency_s, status) once done, else None."""
+        u0 = np.zeros(2, dtype=np.float32)
+        lat = ctypes.c_double()
+        sts = ctypes.c_int32()
+        st = self.L.mppi_server_poll(self.s, ticket, _fp(u0), ctypes.byref(lat), ctypes.byref(sts))
+        if st == A.E_BUSY:
+            return None
+        if st != A.OK:
+            self._err(st, "mppi_server_poll")
+        return u0, lat.value, sts.value
+
+    def wait(self, ticket: int):
+        u0 = np.zeros(2, dtype=np.float32)
+        lat = ctypes.c_double()
+        sts = ctypes.c_int32()
+        st = self.L.mppi_server_wait(self.s, ticket, _fp(u0), ctypes.byref(lat), ctypes.byref(sts))
+        if st != A.OK:
+            self._err(st, "mppi_server_wait")
+        return u0, lat.value, sts.value
+
+    def stats(self) -> dict:
+        s = A.ServerStats()
+        st = self.L.mppi_server_get_stats(self.s, ctypes.byref(s))
+        if st != A.OK:
+            self._err(st, "mppi_server_get_stats")
+        return {f: getattr(s, f) for f, _ in A.ServerStats._fields_}
+
+    def robot_state(self, rid: int):
+        n, T = self.dims[rid]
+        U = np.zeros((T, 2), dtype=np.float32)
+        c = ctypes.c_uint64()
+        st = self.L.mppi_server_get_robot(self.s, rid, _fp(U), ctypes.byref(c))
+        if st != A.OK:
+            self._err(st, "mppi_server_get_robot")
+        return U, int(c.value)

@@ -264,6 +264,14 @@ int mppi_ctrl::alloc_tile_buffers()
 
 extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_t** out)
 {
+    return create_ctrl(cfg, dev, false, out);
+}
+
+// external_scratch: leave the per-iteration sample buffers (noise, costs,
+// exponentials, tile partials) unallocated; the owner (the server) supplies
+// them per launch from its own pool.
+int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool external_scratch, mppi_ctrl** out)
+{
     if (!out) return MPPI_E_INVALID;
     *out = nullptr;
     std::string why = validate_config(cfg);
@@ -274,6 +282,7 @@ extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_
     mppi_ctrl* h = new (std::nothrow) mppi_ctrl();
     if (!h) return MPPI_E_NOMEM;
     h->cfg = *cfg;
+    h->external_scratch = external_scratch;
     h->device = dev ? dev->device : 0;
     int st = MPPI_OK;
     hipError_t e = hipSetDevice(h->device);
@@ -342,9 +351,11 @@ extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_
 
     p.U = static_cast<float*>(h->dalloc(sizeof(float) * 2 * T * kM, &st));
     p.Ustar = static_cast<float*>(h->dalloc(sizeof(float) * T * kM, &st));
-    p.du = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)T * kM * p.Kp, &st));
-    p.S = static_cast<float*>(h->dalloc(sizeof(float) * 2 * (size_t)p.Kp, &st));
-    p.e = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)p.Kp, &st));
+    if (!external_scratch) {
+        p.du = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)T * kM * p.Kp, &st));
+        p.S = static_cast<float*>(h->dalloc(sizeof(float) * 2 * (size_t)p.Kp, &st));
+        p.e = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)p.Kp, &st));
+    }
     p.xref = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)(T + 1) * n, &st));
     p.st = static_cast<CtrlState*>(h->dalloc(sizeof(CtrlState), &st));
     if (st) {
@@ -352,7 +363,7 @@ extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_
         delete h;
         return st;
     }
-    if (!st) st = h->alloc_tile_buffers();
+    if (!st && !external_scratch) st = h->alloc_tile_buffers();
     if (st) {
         set_global_error(h->err);
         delete h;
@@ -372,9 +383,11 @@ extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_
     s0.S_e = 1.0f;
     e = hipMemset(p.U, 0, sizeof(float) * 2 * T * kM);
     if (e == hipSuccess) e = hipMemset(p.Ustar, 0, sizeof(float) * T * kM);
-    if (e == hipSuccess) e = hipMemset(p.du, 0, sizeof(float) * (size_t)T * kM * p.Kp);
-    if (e == hipSuccess) e = hipMemset(p.S, 0, sizeof(float) * 2 * (size_t)p.Kp);
-    if (e == hipSuccess) e = hipMemset(p.e, 0, sizeof(float) * (size_t)p.Kp);
+    if (!external_scratch) {
+        if (e == hipSuccess) e = hipMemset(p.du, 0, sizeof(float) * (size_t)T * kM * p.Kp);
+        if (e == hipSuccess) e = hipMemset(p.S, 0, sizeof(float) * 2 * (size_t)p.Kp);
+        if (e == hipSuccess) e = hipMemset(p.e, 0, sizeof(float) * (size_t)p.Kp);
+    }
     if (e == hipSuccess) e = hipMemset(const_cast<float*>(p.xref), 0, sizeof(float) * (size_t)(T + 1) * n);
     if (e == hipSuccess) e = hipMemcpy(p.st, &s0, sizeof s0, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -397,6 +410,10 @@ int mppi_ctrl::retile()
     const int S = choose_tile_samples(this);
     if (S == p.spt) return MPPI_OK;
     if (tile_chunk_slots(p.J, cfg.T, p.n, S) == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
+    if (external_scratch) {
+        ++version;
+        return configure_tiles(S);
+    }
     int s = sync();
     if (s) return s;
     for (double* ptr : {p.rho_b, p.eta_b, p.f_b}) {

@@ -15,6 +15,7 @@ struct mppi_ctrl {
     bool own_stream = false;
     bool poisoned = false;
     bool tiles_fixed = false;
+    bool external_scratch = false;   // sample buffers supplied per launch by the owner
     uint64_t version = 0;            // bumps whenever DevParams change (batches re-upload)
     uint32_t iter = 0;               // iterations launched; U[iter & 1] holds the warm start
     std::string err;
@@ -47,8 +48,9 @@ struct mppi_ctrl {
 namespace dbas {
 std::string validate_config(const mppi_config* c);
 int heuristic_tile_samples(int K, int J, int T, int n);
-// Autotuned lanes-per-sample for this controller's (model, K, T, J, P).
+// Samples per tile for this controller's (model, K, T, J, P, costmap): measured once per shape.
 int choose_tile_samples(mppi_ctrl* h);
+int create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool external_scratch, mppi_ctrl** out);
 }  // namespace dbas
 
 void set_global_error(const std::string& s);
