@@ -15,6 +15,8 @@ bracketed by device synchronisation.  Also reported:
   * p50/p99 control-step latency of the plain path (host state in, u0 out),
   * the batched path: 64 mixed controllers in one graph-captured persistent
     launch vs the same 64 stepped one after another through the plain path,
+  * the served path: 256 robots sending Poisson 50 Hz request streams to the
+    continuous-batching server (p50/p99 arrival-to-response latency),
   * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -160,6 +162,81 @@ def bench_batched(n_ctrl=64, steps=30, seed=3):
     }
 
 
+def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 << 20, streams=2):
+    """Poisson request streams from `n_robots` robots (sizes as the mixed
+    batch) at `rate_hz` each, closed loop through the host plant, served by the
+    continuous-batching server.  Latency = completion - scheduled arrival, so
+    any lag of this client counts against the server, never for it."""
+    from collections import deque
+
+    from paper_2504_06437_amd.controller import Server
+    from paper_2504_06437_amd.plant import advance
+    wls = W.batch(n_robots, seed)
+    srv = Server(budget_bytes=budget, max_slots=256, streams=streams, max_batch=64)
+    t_setup = time.perf_counter()
+    ids = [srv.add_robot(wl["params"], wl["obstacles"]) for wl in wls]
+    t_setup = time.perf_counter() - t_setup
+    states = [wl["x0"].copy() for wl in wls]
+    # warm-up: one request per robot
+    for i, wl in enumerate(wls):
+        srv.wait(srv.submit(ids[i], states[i], W.reference(wl, states[i])))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    arrivals = []
+    for r in range(n_robots):
+        t = rng.exponential(1.0 / rate_hz)
+        while t < seconds:
+            arrivals.append((t, r))
+            t += rng.exponential(1.0 / rate_hz)
+    arrivals.sort()
+    work = [wl["params"]["K"] * wl["params"]["T"] for wl in wls]
+    pending = [deque() for _ in wls]
+    waiting = set()
+    last_ref = [0.0] * n_robots
+    lat, statuses, served_steps, lag_max = [], [], 0, 0.0
+    t0 = srv.now() + 0.05
+    i, t_end = 0, t0
+    while i < len(arrivals) or waiting:
+        now = srv.now()
+        if i < len(arrivals) and now >= t0 + arrivals[i][0]:
+            t, r = arrivals[i]
+            i += 1
+            lag_max = max(lag_max, now - (t0 + t))
+            ref = None
+            if t - last_ref[r] >= 1.0:
+                ref = W.reference(wls[r], states[r])
+                last_ref[r] = t
+            pending[r].append(srv.submit(ids[r], states[r], ref, t0 + t))
+            waiting.add(r)
+            continue
+        for r in list(waiting):
+            while pending[r]:
+                res = srv.poll(pending[r][0])
+                if res is None:
+                    break
+                pending[r].popleft()
+                u0, l, st = res
+                lat.append(l)
+                statuses.append(st)
+                served_steps += work[r]
+                states[r] = advance(wls[r]["params"], states[r], u0)
+                t_end = max(t_end, srv.now())
+            if not pending[r]:
+                waiting.discard(r)
+    stats = srv.stats()
+    srv.close()
+    span = t_end - t0
+    return {
+        "robots": n_robots, "rate_hz_per_robot": rate_hz, "seconds": seconds, "requests": len(lat),
+        "ok": int(sum(1 for s in statuses if s == 0)),
+        "rollout_steps_per_s": served_steps / span, "requests_per_s": len(lat) / span,
+        "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99), "max_ms": 1e3 * max(lat),
+        "client_lag_max_ms": 1e3 * lag_max, "launches": stats["launches"], "mean_batch": stats["mean_batch"],
+        "deferred_budget": stats["deferred_budget"], "deferred_slots": stats["deferred_slots"],
+        "peak_scratch_bytes": stats["peak_bytes_in_flight"], "budget_bytes": budget, "streams": streams,
+        "setup_s": t_setup,
+    }
+
+
 def cpu_baseline(wl, budget_s=12.0):
     """The FP64 oracle, single-threaded, on whole iterations of the same workload."""
     import oracle
@@ -267,6 +344,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -316,6 +395,9 @@ def main():
     if not args.no_batched:
         print("[bench] batched path: 64 mixed controllers", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
+    if not args.no_served:
+        print(f"[bench] served path: 256 robots x 50 Hz for {args.serve_seconds:g} s", file=sys.stderr, flush=True)
+        out["served"] = bench_served(args.serve_seconds)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
