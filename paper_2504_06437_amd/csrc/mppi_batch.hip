@@ -114,7 +114,7 @@ int choose_tile_samples(mppi_ctrl* h)
     if (autotune_enabled() && p.J > 0 && h->sync() == MPPI_OK) {
         float best = -1.0f;
         for (int cand : {16, 32, 64, 128, 256}) {
-            if (tile_chunk_slots(p.J, p.T, p.n, cand) == 0 || (p.K + cand - 1) / cand > kMaxTiles) continue;
+            if (tile_chunk_steps(p.J, p.T, p.n, cand) == 0 || (p.K + cand - 1) / cand > kMaxTiles) continue;
             const float ms = time_rollout(h, cand, 3);
             if (ms > 0 && (best < 0 || ms < best * 0.97f)) {
                 best = ms;

@@ -104,9 +104,9 @@ inline int state_dim(int model) { return model == MPPI_QUAD6 ? 6 : model == MPPI
 __host__ __device__ inline int obstacle_slots(int J) { return J > 0 ? J : 1; }
 
 constexpr size_t kLdsLimit = 65536;     // dynamic LDS budget of one rollout workgroup
-constexpr int kChunkSlotsMax = 2048;    // (step, sample) input slots staged per chunk
+constexpr int kChunkSlotsMax = 2048;    // most (step, sample) slots in one horizon chunk
 
-// LDS bytes of a rollout tile apart from the chunk's input slots.
+// LDS bytes of a rollout tile apart from the chunk slots.
 __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
 {
     size_t b = 0;
@@ -116,28 +116,36 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
+    b += 16;                                    // work counters
     return b;
 }
 
-constexpr int kSlotBytes = 32;          // per (step, sample): inputs (float4) + pose (float4)
+// Per (step, sample) slot, double-buffered: inputs (float4), pose (float4),
+// fused barrier (float).
+constexpr int kSlotBytes = 2 * (16 + 16 + 4);
 
-// (step, sample) slots per horizon chunk: a whole number of steps for the
-// tile's S samples, within the LDS budget.  0 when even one step does not fit
-// (such a configuration is rejected).
-__host__ __device__ inline int tile_chunk_slots(int J, int T, int n, int S)
+// First chunk of the rollout pipeline: about a tenth of the horizon.
+__host__ __device__ inline int tile_first_chunk(int T) { return (T + 9) / 10; }
+
+// Steps per horizon chunk of the rollout pipeline after the first: a third
+// of the rest of the horizon, within the LDS budget and kChunkSlotsMax.
+// 0 when even one step does not fit (such a configuration is rejected).
+__host__ __device__ inline int tile_chunk_steps(int J, int T, int n, int S)
 {
     const size_t fixed = tile_fixed_lds(J, T, n);
     if (fixed + (size_t)S * kSlotBytes > kLdsLimit) return 0;
-    long slots = (long)((kLdsLimit - fixed) / kSlotBytes);
-    if (slots > kChunkSlotsMax) slots = kChunkSlotsMax;
-    if (slots > (long)T * S) slots = (long)T * S;
-    return (int)(slots / S * S);
+    long fit = (long)((kLdsLimit - fixed) / ((size_t)S * kSlotBytes));
+    if (fit > kChunkSlotsMax / S) fit = kChunkSlotsMax / S;
+    long tc = (T - tile_first_chunk(T) + 2) / 3;
+    if (tc > fit) tc = fit;
+    if (tc < 1) tc = 1;
+    return (int)tc;
 }
 
 // Dynamic LDS bytes one rollout tile of this controller needs.
 inline size_t tile_lds_bytes(int J, int T, int n, int S)
 {
-    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_slots(J, T, n, S) * kSlotBytes;
+    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_steps(J, T, n, S) * S * kSlotBytes;
 }
 
 // Kernel launchers (mppi_kernels.hip).

@@ -1,33 +1,35 @@
 // HIP kernels (gfx950) of one DBaS-Log-MPPI iteration.
 //
 //   rollout kernel  -- one workgroup per tile of S samples.  The horizon is
-//                      processed in chunks of steps, each in four phases:
-//                       (1) inputs: the whole workgroup draws the chunk's
-//                           Philox4x32-10 normal x log-normal noise (Sec. IV-C)
-//                           for every (step, sample) and turns it into the
-//                           state-independent terms (saturated inputs, their
-//                           model terms, the control cost of Alg. 1), in LDS;
-//                       (2) dynamics: one lane per sample integrates the state
-//                           (eq. veh_dyn), storing the pose of every step and
-//                           adding the tracking and control costs;
-//                       (3) barrier: every thread takes (step, sample) items
-//                           and evaluates the fused barrier over the obstacles
-//                           (LDS broadcast) and the costmap -- the bulk of the
-//                           work, with no dependence between items;
-//                       (4) barrier state: one lane per sample runs the
-//                           recursion of eq. barrier_update and adds R_B beta
-//                           (Alg. 1, eq. cost-to-go_bas) to its compensated
-//                           FP32 cost.
-//                      The tile then forms its own min-shifted exponentials and
-//                      the tile sums eta_b = sum e_k and N_b[t][c] =
+//                      cut into chunks that flow through a pipeline of
+//                      workgroup-wide stages; per chunk:
+//                       - inputs: Philox4x32-10 normal x log-normal noise
+//                         (Sec. IV-C) for every (step, sample), turned into the
+//                         state-independent terms (saturated inputs, their
+//                         model terms, the control cost of Alg. 1), in LDS;
+//                       - dynamics: one lane per sample integrates the state
+//                         (eq. veh_dyn), storing the pose of every step and
+//                         adding the tracking and control costs;
+//                       - barrier: every (step, sample) is split over lanes
+//                         that each take a range of obstacles (LDS) and the
+//                         costmap -- the bulk of the work, no dependence
+//                         between items;
+//                       - barrier state: one lane per sample runs the
+//                         recursion of eq. barrier_update and adds R_B beta
+//                         (Alg. 1, eq. cost-to-go_bas) to its compensated
+//                         FP32 cost.
+//                      The sequential parts (dynamics, barrier state) of one
+//                      chunk overlap the parallel parts of its neighbours.
+//                      The tile then forms its own min-shifted exponentials
+//                      and the tile sums eta_b = sum e_k and N_b[t][c] =
 //                      sum e_k du_k.  Tiles never wait for one another.
-//   update kernel   -- one workgroup per controller: merges the tile minima
-//                      and normalisers (eq. control_update: rho = min S, eta),
-//                      then one wave per control row (t, c): U*[t][c] =
-//                      U[t][c] + sum_b f_b N_b[t][c] / eta, coalesced over
-//                      tiles; writes U* and the shifted warm start (Alg. 1
-//                      closing loop) into the other half of a double buffer,
-//                      and u0*.
+//   update kernel   -- one workgroup per four control rows (t, c).  Every
+//                      workgroup merges the tile minima and normalisers
+//                      itself (eq. control_update: rho = min S, eta), then
+//                      one wave per row forms U*[t][c] = U[t][c] +
+//                      sum_b f_b N_b[t][c] / eta, coalesced over tiles, and
+//                      writes U* and the shifted warm start (Alg. 1 closing
+//                      loop) into the other half of a double buffer, and u0*.
 //
 // Positions are handled in a frame centred on the iteration's start position
 // (obstacles, reference and costmap offset are translated once in FP64), so
@@ -318,18 +320,23 @@ template <> struct Model<MPPI_CAR> {
     }
 };
 
-// LDS carve-up of one rollout tile (sizes: tile_fixed_lds + chunk slots).
+// LDS carve-up of one rollout tile (sizes: tile_fixed_lds, then two chunks of
+// per-(step, sample) slots).
 struct TileLds {
-    float4* obs;     // [J] (ox, oy, -r^2, 0), local frame
-    float2* U;       // [T]
-    float* ref;      // [(T+1) n], local frame
-    double* e;       // [kMaxTile] tile exponentials
-    double* slots;   // [16] block-reduction slots
-    float4* in;      // [chunk] per (step, sample): (f0, f1, control cost, 0); then barrier partial sums
-    float4* pose;    // [chunk] per (step, sample): (x, y, cos theta, sin theta)
+    float4* obs;      // [J] (ox, oy, -r^2, 0), local frame
+    float2* U;        // [T]
+    float* ref;       // [(T+1) n], local frame
+    double* e;        // [kMaxTile] tile exponentials
+    double* slots;    // [16] block-reduction slots
+    int* work;        // [4] work counters of the barrier stages
+    // chunk slots, two buffers each (buffer b at offset b * cs):
+    float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, 0)
+    float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
+    float* bval;      // [2][cs] per (step, sample): fused barrier
+    int cs;
 };
 
-__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int chunk)
+__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int cs)
 {
     TileLds L;
     size_t off = 0;
@@ -344,9 +351,14 @@ __device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int 
     off += (size_t)kMaxTile * 8;
     L.slots = reinterpret_cast<double*>(smem + off);
     off += 16 * 8;
+    L.work = reinterpret_cast<int*>(smem + off);
+    off += 16;
+    L.cs = cs;
     L.in = reinterpret_cast<float4*>(smem + off);
-    off += (size_t)chunk * 16;
+    off += (size_t)2 * cs * 16;
     L.pose = reinterpret_cast<float4*>(smem + off);
+    off += (size_t)2 * cs * 16;
+    L.bval = reinterpret_cast<float*>(smem + off);
     return L;
 }
 
@@ -358,40 +370,65 @@ struct X0 {
 constexpr int kRollWaves = kRollBlock / kWave;
 constexpr int kUpdWaves = kUpdBlock / kWave;
 
-// Fused barrier of a (local-frame) pose, cooperatively over the block.
-__device__ float fused_barrier_block(const DevParams& p, const TileLds& L, int P, float px0, float py0, float th,
-                                     float inv_res, float offx, float offy)
+template <int NW>
+__device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 {
-    float sth, cth;
-    heading_sincos(th, sth, cth);
-    float acc = 0.0f;
+    v.x = wave_sum_f(v.x);
+    v.y = wave_sum_f(v.y);
+    float* s = reinterpret_cast<float*>(slots);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s[2 * (threadIdx.x >> 6)] = v.x;
+        s[2 * (threadIdx.x >> 6) + 1] = v.y;
+    }
+    __syncthreads();
+    float2 r = make_float2(s[0], s[1]);
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+        r.x += s[2 * i];
+        r.y += s[2 * i + 1];
+    }
+    return r;
+}
+
+// Fused barrier of two (local-frame) poses a and b, cooperatively over the block.
+__device__ float2 fused_barrier_block2(const DevParams& p, const TileLds& L, int P, float ax, float ay, float ath,
+                                       float bx, float by, float bth, float inv_res, float offx, float offy)
+{
+    float sa, ca, sb, cb;
+    heading_sincos(ath, sa, ca);
+    heading_sincos(bth, sb, cb);
+    float acc_a = 0.0f, acc_b = 0.0f;
     const int J = p.J;
     for (int idx = threadIdx.x; idx < P * J; idx += kRollBlock) {
         const int i = idx / J, j = idx - i * J;
-        const float a = p.shape[i][0], b = p.shape[i][1];
-        const float px = px0 + (a * cth - b * sth);
-        const float py = py0 + (a * sth + b * cth);
+        const float u = p.shape[i][0], w = p.shape[i][1];
         const float4 o = L.obs[j];
-        const float dx = px - o.x, dy = py - o.y;
-        acc += barrier_rcp(fmaf(dx, dx, fmaf(dy, dy, o.z)), p.h_eps);
+        const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
+        const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
+        const float dax = pax - o.x, day = pay - o.y, dbx = pbx - o.x, dby = pby - o.y;
+        acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.z)), p.h_eps);
+        acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.z)), p.h_eps);
     }
     if (p.sdf != nullptr && (int)threadIdx.x < P) {
         const int i = threadIdx.x;
-        const float a = p.shape[i][0], b = p.shape[i][1];
-        const float px = px0 + (a * cth - b * sth);
-        const float py = py0 + (a * sth + b * cth);
-        acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
-                           p.h_eps);
+        const float u = p.shape[i][0], w = p.shape[i][1];
+        const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
+        const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
+        acc_a += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pax, inv_res, offx), fmaf(pay, inv_res, offy)),
+                             p.h_eps);
+        acc_b += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pbx, inv_res, offx), fmaf(pby, inv_res, offy)),
+                             p.h_eps);
     }
-    return block_sum_f<kRollWaves>(acc, L.slots);
+    return block_sum_f2<kRollWaves>(make_float2(acc_a, acc_b), L.slots);
 }
 
 // Part of the fused barrier of one pose: every shape point against obstacles
-// [j0, j1) (read by LDS broadcast: the lanes of a wave read the same one),
-// plus the costmap terms when `with_map`.
+// j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus the costmap terms
+// when `with_map`.
 template <int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa,
-                                                    const float* sb, float4 pose, int j0, int j1, bool with_map,
+                                                    const float* sb, float4 pose, int j0, int js, bool with_map,
                                                     float inv_res, float offx, float offy)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
@@ -399,12 +436,13 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
     float px[PM], py[PM];
 #pragma unroll
     for (int i = 0; i < PM; ++i) {
-        px[i] = pose.x + (sa[i] * pose.z - sb[i] * pose.w);
-        py[i] = pose.y + (sa[i] * pose.w + sb[i] * pose.z);
+        px[i] = fmaf(sa[i], pose.z, fmaf(-sb[i], pose.w, pose.x));
+        py[i] = fmaf(sa[i], pose.w, fmaf(sb[i], pose.z, pose.y));
     }
     float acc = 0.0f, acc2 = 0.0f;
+    const int J = p.J;
 #pragma unroll 2
-    for (int j = j0; j < j1; ++j) {
+    for (int j = j0; j < J; j += js) {
         const float4 o = L.obs[j];
         if constexpr (PT != 0) {
             float h[PM];
@@ -441,21 +479,44 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 // ---------------------------------------------------------------------------
 // One tile of S samples: rollout and the tile's softmax partials.
 // PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX).
+//
+// The horizon is cut into chunks of tc steps that flow through a pipeline of
+// workgroup-wide stages.  In stage k:
+//   * the waves that own samples (lane tid < S) first run the barrier-state
+//     recursion over chunk k-2 and then integrate the dynamics of chunk k --
+//     the two sequential parts, one lane per sample;
+//   * the other waves draw the noise and inputs of chunk k+1;
+//   * then every wave takes units of the fused-barrier work of chunk k-1 from
+//     an LDS work counter (a wave that owns samples joins when its sequential
+//     part is done).
+// Every (step, sample) of a chunk is split over nsp adjacent lanes; lane sp
+// of the group takes obstacles sp, sp + nsp, ..., so a wave's lanes read one
+// contiguous run of obstacles at a time; the nsp partial sums meet by wave
+// shuffles.
+// Inputs, poses and barrier values are double-buffered by chunk parity.
 // ---------------------------------------------------------------------------
 template <int MODEL, int S, int PT>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int NS = Model<MODEL>::NS;
     constexpr int PM = PT ? PT : MPPI_PMAX;
+    constexpr int DW = (S + kWave - 1) / kWave;     // waves that own samples
+    constexpr int POOL0 = DW * kWave;               // first thread of the noise pool
     static_assert(S >= 16 && S <= kMaxTile && (S & (S - 1)) == 0, "tile size");
-    const int tid = threadIdx.x;
+    static_assert(POOL0 < kRollBlock, "the noise pool needs a wave");
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int J = p.J, T = p.T, K = p.K, Kp = p.Kp;
     const int P = PT ? PT : p.P;
-    // (step, sample) slots per chunk (the host only configures tiles whose
-    // chunk holds at least one step)
-    const int chunk = tile_chunk_slots(J, T, NS, S);
-    const int tcs = max(1, chunk / S);
-    const TileLds L = carve(smem, J, T, NS, chunk);
+    // the host only configures tiles whose chunk holds at least one step
+    const int tc = tile_chunk_steps(J, T, NS, S);
+    // chunk 0 is shorter: its dynamics run while the barrier pool has no
+    // poses yet
+    const int tc0 = min(tile_first_chunk(T), tc);
+    const int nch = 1 + (T - tc0 + tc - 1) / tc;
+    const TileLds L = carve(smem, J, T, NS, tc * S);
+    const CtrlState* cs_in = p.st;
+    const float S_e = cs_in->S_e;
+    const uint64_t ctr = cs_in->counter;
 
     const float* Uin = p.U + (size_t)(xs.parity & 1u) * T * kM;
 
@@ -481,21 +542,19 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     __syncthreads();
 
     // beta_0 = fused B(h(x0)); beta_d = fused B(h(x_d)), x_d = x_ref[T].
-    const float beta0 = fused_barrier_block(p, L, P, 0.0f, 0.0f, xs.v[2], inv_res, offx, offy);
-    const float beta_d = fused_barrier_block(p, L, P, L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
-                                             inv_res, offx, offy);
+    const float2 b0d = fused_barrier_block2(p, L, P, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1],
+                                            L.ref[T * NS + 2], inv_res, offx, offy);
+    const float beta0 = b0d.x, beta_d = b0d.y;
 
     // ---- setup: lanes 0..S-1 own one sample each ----
     const bool owner = tid < S;
     const int k = tile * S + tid;
     const bool valid = owner && k < K;
 
-    const float S_e = p.st->S_e;
     const float sqS = sqrtf(S_e);
     const float scale0 = sqS * p.sigma[0], scale1 = sqS * p.sigma[1];
     const float cw0 = p.sigma[0] > 0.0f ? p.gamma_u / (S_e * p.sigma[0] * p.sigma[0]) : 0.0f;
     const float cw1 = p.sigma[1] > 0.0f ? p.gamma_u / (S_e * p.sigma[1] * p.sigma[1]) : 0.0f;
-    const uint64_t ctr = p.st->counter;
     const uint32_t c_lo = (uint32_t)ctr, c_hi = (uint32_t)(ctr >> 32);
 
     float x[NS];
@@ -507,17 +566,16 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     heading_sincos(x[2], sth, cth);
     // eq. barrier_update is linear in beta, so beta_t = bv_t + c_t with the
     // sample-dependent part bv_t = b_t + gamma_B bv_{t-1} (bv_0 = beta_0) and
-    // the common part c_t = gamma_B (c_{t-1} - beta_d) (c_0 = 0).  The common
-    // part's cost R_B sum_t c_t is the same for every sample and is added in
-    // FP64 (cshift), so a large beta_d cannot swamp the FP32 running sum.
+    // the common part c_t = gamma_B (c_{t-1} - beta_d) (c_0 = 0), whose sum is
+    // -beta_d gamma_B/(1-gamma_B) (T - gamma_B (1-gamma_B^T)/(1-gamma_B)).
+    // The common part's cost R_B sum_t c_t is the same for every sample and is
+    // added in FP64 (cshift), so a large beta_d cannot swamp the FP32 sums.
     float beta = beta0;
-    double cshift = 0.0;
+    double cshift;
     {
-        double c = 0.0;
-        for (int t = 0; t < T; ++t) {
-            c = (double)p.gamma_b * (c - (double)beta_d);
-            cshift += (double)p.r_b * c;
-        }
+        const double g = (double)p.gamma_b;
+        const double geo = g * (1.0 - pow(g, (double)T)) / (1.0 - g);
+        cshift = (double)p.r_b * (-(double)beta_d * g / (1.0 - g) * ((double)T - geo));
     }
     float S_hi = 0.0f, S_lo = 0.0f;
 
@@ -527,20 +585,16 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         sa[i] = (PT || i < P) ? p.shape[i][0] : 0.0f;
         sb[i] = (PT || i < P) ? p.shape[i][1] : 0.0f;
     }
-    float* bpart = reinterpret_cast<float*>(L.in);     // phase 3 output, over the spent inputs
 
-    for (int t0 = 0; t0 < T; t0 += tcs) {
-        const int tc = min(tcs, T - t0);
-        const int items = tc * S;
-        // barrier items are split over nsp obstacle ranges (1, 2 or 4) when
-        // there are few items, so that every thread has work
-        int nsp = 1;
-        while (nsp < 4 && items * nsp < 2 * kRollBlock && J >= 16 * nsp) nsp *= 2;
-        __syncthreads();
-        // (1) inputs of every (step, sample) of the chunk
-        for (int idx = tid; idx < items; idx += kRollBlock) {
-            const int s = idx & (S - 1), tt = idx / S;
-            const int t = t0 + tt;
+    auto chunk_t0 = [&](int c) { return c == 0 ? 0 : tc0 + (c - 1) * tc; };
+    auto chunk_len = [&](int c) { return c == 0 ? tc0 : min(tc, T - chunk_t0(c)); };
+
+    // inputs of every (step, sample) of chunk c, over threads [first, block)
+    auto inputs_chunk = [&](int c, int first) __attribute__((always_inline)) {
+        const int t0 = chunk_t0(c), items = chunk_len(c) * S;
+        float4* dst = L.in + (c & 1) * L.cs;
+        for (int idx = tid - first; idx < items; idx += kRollBlock - first) {
+            const int s = idx & (S - 1), t = t0 + idx / S;
             const int kk = tile * S + s;
             const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), p.seed_lo, p.seed_hi);
             const float2 z = nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
@@ -550,53 +604,91 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
             float f0, f1;
             Model<MODEL>::inputs(p, s0, s1, f0, f1);
-            L.in[idx] = make_float4(f0, f1, cw0 * u.x * v0 + cw1 * u.y * v1, 0.0f);
+            dst[idx] = make_float4(f0, f1, cw0 * u.x * v0 + cw1 * u.y * v1, 0.0f);
             if (kk < K) {
                 p.du[(size_t)(2 * t) * Kp + kk] = z.x;
                 p.du[(size_t)(2 * t + 1) * Kp + kk] = z.y;
             }
         }
-        __syncthreads();
-        // (2) dynamics: one lane per sample; poses to LDS, tracking + control cost
-        if (owner) {
-            float4 nin = L.in[tid];
-            for (int tt = 0; tt < tc; ++tt) {
-                const float4 in = nin;
-                if (tt + 1 < tc) nin = L.in[(tt + 1) * S + tid];
-                const float* rf = L.ref + (t0 + tt + 1) * NS;
-                float ref[NS];
+    };
+
+    // dynamics of chunk c (owner lanes): poses to LDS, tracking + control cost
+    auto dynamics_chunk = [&](int c) __attribute__((always_inline)) {
+        const int t0 = chunk_t0(c), n = chunk_len(c);
+        const float4* src = L.in + (c & 1) * L.cs;
+        float4* pz = L.pose + (c & 1) * L.cs;
+        float4 nin = src[tid];
+        for (int tt = 0; tt < n; ++tt) {
+            const float4 in = nin;
+            if (tt + 1 < n) nin = src[(tt + 1) * S + tid];
+            const float* rf = L.ref + (t0 + tt + 1) * NS;
+            float ref[NS];
 #pragma unroll
-                for (int a = 0; a < NS; ++a) ref[a] = rf[a];
-                Model<MODEL>::step(p, x, in.x, in.y, sth, cth);
-                heading_sincos(x[2], sth, cth);
-                L.pose[tt * S + tid] = make_float4(x[0], x[1], cth, sth);
-                float q = 0.0f;
+            for (int a = 0; a < NS; ++a) ref[a] = rf[a];
+            Model<MODEL>::step(p, x, in.x, in.y, sth, cth);
+            heading_sincos(x[2], sth, cth);
+            pz[tt * S + tid] = make_float4(x[0], x[1], cth, sth);
+            float q = 0.0f;
 #pragma unroll
-                for (int a = 0; a < NS; ++a) {
-                    const float d = x[a] - ref[a];
-                    q = fmaf(p.Q[a], d * d, q);
-                }
-                two_sum_acc(S_hi, S_lo, q + in.z);
+            for (int a = 0; a < NS; ++a) {
+                const float d = x[a] - ref[a];
+                q = fmaf(p.Q[a], d * d, q);
             }
+            two_sum_acc(S_hi, S_lo, q + in.z);
         }
+    };
+
+    // barrier-state recursion over chunk c (owner lanes) and its cost
+    auto beta_chunk = [&](int c) __attribute__((always_inline)) {
+        const int n = chunk_len(c);
+        const float* bv = L.bval + (c & 1) * L.cs;
+        float nb = bv[tid];
+        for (int tt = 0; tt < n; ++tt) {
+            const float b = nb;
+            if (tt + 1 < n) nb = bv[(tt + 1) * S + tid];
+            beta = fmaf(p.gamma_b, beta, b);
+            two_sum_acc(S_hi, S_lo, p.r_b * beta);
+        }
+    };
+
+    // fused barrier of every (step, sample) of chunk c, in units of one wave
+    // taken from the work counter
+    auto barrier_chunk = [&](int c, int* counter) __attribute__((always_inline)) {
+        const int items = chunk_len(c) * S;
+        int lg = 0;
+        while (lg < 6 && (items << lg) < 48 * kWave && J >= (8 << lg)) ++lg;
+        const int nsp = 1 << lg;
+        const int units = ((items << lg) + kWave - 1) / kWave;
+        const float4* pz = L.pose + (c & 1) * L.cs;
+        float* bv = L.bval + (c & 1) * L.cs;
+        for (;;) {
+            int u = 0;
+            if (lane == 0) u = atomicAdd(counter, 1);
+            u = __shfl(u, 0);
+            if (u >= units) break;
+            const int g = u * kWave + lane;
+            const int item = g >> lg, sp = g & (nsp - 1);
+            float part = 0.0f;
+            if (item < items)
+                part = fused_barrier_pose<PT>(p, L, P, sa, sb, pz[item], sp, nsp, has_map && sp == 0, inv_res, offx,
+                                              offy);
+            for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
+            if (sp == 0 && item < items) bv[item] = part;
+        }
+    };
+
+    inputs_chunk(0, 0);
+    __syncthreads();
+    for (int st_k = 0; st_k <= nch + 1; ++st_k) {
+        if (tid == 0) L.work[(st_k + 1) & 1] = 0;      // counter of the next stage
+        if (wave < DW) {
+            if (owner && st_k >= 2) beta_chunk(st_k - 2);
+            if (owner && st_k < nch) dynamics_chunk(st_k);
+        } else if (st_k + 1 < nch) {
+            inputs_chunk(st_k + 1, POOL0);
+        }
+        if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1, &L.work[st_k & 1]);
         __syncthreads();
-        // (3) fused barrier of every (step, sample), over nsp obstacle ranges
-        for (int u = tid; u < items * nsp; u += kRollBlock) {
-            const int sp = u / items, idx = u - sp * items;
-            const int j0 = sp * J / nsp, j1 = (sp + 1) * J / nsp;
-            bpart[sp * chunk + idx] = fused_barrier_pose<PT>(p, L, P, sa, sb, L.pose[idx], j0, j1,
-                                                             has_map && sp == 0, inv_res, offx, offy);
-        }
-        __syncthreads();
-        // (4) barrier state and its cost
-        if (owner) {
-            for (int tt = 0; tt < tc; ++tt) {
-                float b = bpart[tt * S + tid];
-                for (int sp = 1; sp < nsp; ++sp) b += bpart[sp * chunk + tt * S + tid];
-                beta = fmaf(p.gamma_b, beta, b);
-                two_sum_acc(S_hi, S_lo, p.r_b * beta);
-            }
-        }
     }
     if (owner) {
         const float* rf = L.ref + T * NS;
@@ -610,10 +702,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     }
 
     // ---- tile softmax partials ----
-    if (valid) {
-        p.S[k] = S_hi;
-        p.S[Kp + k] = S_lo;
-    }
+    // (global stores come after the block reductions, whose barriers would
+    // otherwise wait for them)
     const double Sd = ((double)S_hi + (double)S_lo) + cshift;
     const bool ok = valid && isfinite(Sd);
     const double rho_b = block_min_d<kRollWaves>(ok ? Sd : INFINITY, L.slots);
@@ -626,7 +716,6 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         ek = use64 ? exp(-d) : (double)expf(-(float)d);
     }
     if (owner) L.e[tid] = ek;
-    if (valid) p.e[k] = (float)ek;
     double eta_b;
     if (use64) eta_b = block_sum_d<kRollWaves>(ek, L.slots);
     else eta_b = (double)block_sum_f<kRollWaves>((float)ek, L.slots);
@@ -662,6 +751,11 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             out = (double)a;
         }
         if (part == 0 && r < R) p.partN[(size_t)r * p.tiles + tile] = any ? out : 0.0;
+    }
+    if (valid) {
+        p.S[k] = S_hi;
+        p.S[Kp + k] = S_lo;
+        p.e[k] = (float)ek;
     }
     if (tid == 0) {
         p.rho_b[tile] = rho_b;

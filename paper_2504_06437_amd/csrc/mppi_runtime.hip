@@ -230,7 +230,7 @@ int heuristic_tile_samples(int K, int J, int T, int n)
 {
     int S = 16;
     while (S < 64 && (long)K / (2 * S) >= 256) S *= 2;
-    while (S > 16 && tile_chunk_slots(J, T, n, S) == 0) S /= 2;
+    while (S > 16 && tile_chunk_steps(J, T, n, S) == 0) S /= 2;
     while (S < kMaxTile && (K + S - 1) / S > kMaxTiles) S *= 2;
     return S;
 }
@@ -239,7 +239,7 @@ int heuristic_tile_samples(int K, int J, int T, int n)
 
 int mppi_ctrl::configure_tiles(int S)
 {
-    if (!tile_samples_supported(S) || tile_chunk_slots(p.J, cfg.T, p.n, S) == 0)
+    if (!tile_samples_supported(S) || tile_chunk_steps(p.J, cfg.T, p.n, S) == 0)
         return fail(MPPI_E_INVALID, "J=%d obstacles with T=%d do not fit the rollout's LDS budget at %d samples per tile",
                     p.J, cfg.T, S);
     p.spt = S;
@@ -409,7 +409,7 @@ int mppi_ctrl::retile()
     if (tiles_fixed) return MPPI_OK;
     const int S = choose_tile_samples(this);
     if (S == p.spt) return MPPI_OK;
-    if (tile_chunk_slots(p.J, cfg.T, p.n, S) == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
+    if (tile_chunk_steps(p.J, cfg.T, p.n, S) == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
     if (external_scratch) {
         ++version;
         return configure_tiles(S);
@@ -434,7 +434,7 @@ extern "C" int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int3
     CHECK_HANDLE(h);
     if (J < 0 || J > MPPI_JMAX) return h->fail(MPPI_E_INVALID, "J=%d outside 0..%d", J, MPPI_JMAX);
     if (J > 0 && !cxcyr) return h->fail(MPPI_E_INVALID, "obstacles pointer is NULL");
-    if (tile_chunk_slots(J, h->cfg.T, h->p.n, h->tiles_fixed ? h->p.spt : 16) == 0)
+    if (tile_chunk_steps(J, h->cfg.T, h->p.n, h->tiles_fixed ? h->p.spt : 16) == 0)
         return h->fail(MPPI_E_INVALID, "J=%d obstacles with T=%d exceed the rollout's LDS budget", J, h->cfg.T);
     std::vector<float> tmp;
     if (J > 0 && mem == MPPI_MEM_HOST) {
