@@ -80,6 +80,9 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *  - h_eps in [1e-9, 1e6].
  *  - tile_samples: samples per rollout workgroup (16, 32, 64, 128 or 256);
  *    0 lets the autotuner choose (per model, K, T, J, P).
+ *  - export_noise: 0 (default) -- the noise lives only inside the rollout
+ *    kernel and is never stored; 1 -- every iteration also writes it to
+ *    device memory (K*T*8 bytes) so that mppi_get_noise can return it.
  */
 typedef struct mppi_config {
     uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
@@ -98,7 +101,8 @@ typedef struct mppi_config {
     int32_t normaliser;            /* mppi_normaliser */
     int32_t init_mode;             /* mppi_init_mode */
     int32_t tile_samples;          /* 0 = autotune */
-    int32_t reserved[7];           /* must be zero */
+    int32_t export_noise;          /* 1: also store each iteration's noise (mppi_get_noise) */
+    int32_t reserved[6];           /* must be zero */
 } mppi_config;
 
 /* Where a handle runs.  stream: a hipStream_t owned by the caller (NULL: the
@@ -188,7 +192,7 @@ int mppi_get_controls(mppi_t* h, float* U);              /* warm start, T*2 */
 int mppi_get_last_optimal(mppi_t* h, float* Ustar);      /* U* before the shift, T*2 */
 int mppi_get_costs(mppi_t* h, double* S);                /* S_k, K (compensated sum as FP64) */
 int mppi_get_weights(mppi_t* h, double* w);              /* normalised weights, K */
-int mppi_get_noise(mppi_t* h, float* du);                /* du[k][t][c], K*T*2 */
+int mppi_get_noise(mppi_t* h, float* du);                /* du[k][t][c], K*T*2; needs export_noise */
 int mppi_get_step_info(mppi_t* h, mppi_step_info* info);
 /* Raw Philox4x32-10 words of every (k, t) for the given counter:
  * words[(k*T + t)*4 + i], from the same device function the sampler uses. */

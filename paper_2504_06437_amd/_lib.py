@@ -51,7 +51,8 @@ class Config(ctypes.Structure):
         ("Q", ctypes.c_float * NMAX), ("Qf", ctypes.c_float * NMAX),
         ("P", ctypes.c_int32), ("shape", (ctypes.c_float * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("normaliser", ctypes.c_int32), ("init_mode", ctypes.c_int32),
-        ("tile_samples", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("tile_samples", ctypes.c_int32), ("export_noise", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 

@@ -54,6 +54,7 @@ def make_config(params: dict) -> A.Config:
     c.normaliser = A.NORMALISER[params.get("normaliser", "auto")]
     c.init_mode = A.INIT_MODE[params.get("init_mode", "repeat")]
     c.tile_samples = int(params.get("tile_samples", 0))
+    c.export_noise = int(bool(params.get("export_noise", False)))
     return c
 
 

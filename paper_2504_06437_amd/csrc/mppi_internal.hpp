@@ -53,13 +53,13 @@ struct DevParams {
     uint32_t seed_lo, seed_hi;
     int32_t map_w, map_h;
     float map_x0, map_y0, map_res;
-    int32_t pad;
+    int32_t export_noise;    // 1: the rollout also stores the noise into du
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
     const float* xref;       // [T+1][n] world frame
     float* U;                // [2][T][2] warm start, double-buffered by iteration parity
     float* Ustar;            // [T][2] optimal sequence of the last iteration (before the shift)
-    float* du;               // [T][2][Kp] noise
+    float* du;               // [T][2][Kp] noise (only with export_noise)
     float* S;                // [2][Kp] compensated cost: hi at [k], lo at [Kp + k]
     float* e;                // [Kp] tile-local exponentials exp(-(S_k - rho_tile)/lambda)
     double* rho_b;           // [tiles] tile minimum cost
@@ -116,7 +116,7 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
-    b += 16;                                    // work counters
+    b += 32;                                    // work counters, cshift, beta_d
     return b;
 }
 
@@ -142,10 +142,19 @@ __host__ __device__ inline int tile_chunk_steps(int J, int T, int n, int S)
     return (int)tc;
 }
 
+// Does the tile keep its whole noise (T x S float2) in LDS for the epilogue,
+// or draw it again there?
+__host__ __device__ inline bool tile_keeps_noise(int J, int T, int n, int S)
+{
+    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_steps(J, T, n, S) * S * kSlotBytes + (size_t)T * S * 8 <=
+           kLdsLimit;
+}
+
 // Dynamic LDS bytes one rollout tile of this controller needs.
 inline size_t tile_lds_bytes(int J, int T, int n, int S)
 {
-    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_steps(J, T, n, S) * S * kSlotBytes;
+    return tile_fixed_lds(J, T, n) + (size_t)tile_chunk_steps(J, T, n, S) * S * kSlotBytes +
+           (tile_keeps_noise(J, T, n, S) ? (size_t)T * S * 8 : 0);
 }
 
 // Kernel launchers (mppi_kernels.hip).

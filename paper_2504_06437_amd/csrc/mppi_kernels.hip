@@ -174,6 +174,15 @@ __device__ __forceinline__ float block_sum_f(float v, double* slots)
     return r;
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores issued
+// before it may still be in flight after it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Compensated accumulation (Knuth's TwoSum): hi + lo carries the sum exactly
 // up to the rounding of lo.
 __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x)
@@ -328,15 +337,17 @@ struct TileLds {
     float* ref;       // [(T+1) n], local frame
     double* e;        // [kMaxTile] tile exponentials
     double* slots;    // [16] block-reduction slots
-    int* work;        // [4] work counters of the barrier stages
+    int* work;        // [2] work counters of the barrier stages, then
+                      // cshift (double, at byte 8)
     // chunk slots, two buffers each (buffer b at offset b * cs):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, 0)
     float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
     float* bval;      // [2][cs] per (step, sample): fused barrier
+    float2* nz;       // [T][S] the tile's noise, when it fits (else null)
     int cs;
 };
 
-__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int cs)
+__device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int cs, bool keep_noise)
 {
     TileLds L;
     size_t off = 0;
@@ -352,13 +363,15 @@ __device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int 
     L.slots = reinterpret_cast<double*>(smem + off);
     off += 16 * 8;
     L.work = reinterpret_cast<int*>(smem + off);
-    off += 16;
+    off += 32;
     L.cs = cs;
     L.in = reinterpret_cast<float4*>(smem + off);
     off += (size_t)2 * cs * 16;
     L.pose = reinterpret_cast<float4*>(smem + off);
     off += (size_t)2 * cs * 16;
     L.bval = reinterpret_cast<float*>(smem + off);
+    off += (size_t)2 * cs * 4;
+    L.nz = keep_noise ? reinterpret_cast<float2*>(smem + off) : nullptr;
     return L;
 }
 
@@ -370,6 +383,7 @@ struct X0 {
 constexpr int kRollWaves = kRollBlock / kWave;
 constexpr int kUpdWaves = kUpdBlock / kWave;
 
+// Sum of a float pair over the block (NW waves); every thread gets it.
 template <int NW>
 __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 {
@@ -391,16 +405,19 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
     return r;
 }
 
-// Fused barrier of two (local-frame) poses a and b, cooperatively over the block.
-__device__ float2 fused_barrier_block2(const DevParams& p, const TileLds& L, int P, float ax, float ay, float ath,
-                                       float bx, float by, float bth, float inv_res, float offx, float offy)
+// This thread's share, over threads [first, block), of the fused barrier at
+// two (local-frame) poses a and b.
+__device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int P, int first, float ax, float ay,
+                                       float ath, float bx, float by, float bth, float inv_res, float offx,
+                                       float offy)
 {
     float sa, ca, sb, cb;
     heading_sincos(ath, sa, ca);
     heading_sincos(bth, sb, cb);
     float acc_a = 0.0f, acc_b = 0.0f;
     const int J = p.J;
-    for (int idx = threadIdx.x; idx < P * J; idx += kRollBlock) {
+    const int i0 = (int)threadIdx.x - first;
+    for (int idx = i0; idx < P * J; idx += kRollBlock - first) {
         const int i = idx / J, j = idx - i * J;
         const float u = p.shape[i][0], w = p.shape[i][1];
         const float4 o = L.obs[j];
@@ -410,9 +427,8 @@ __device__ float2 fused_barrier_block2(const DevParams& p, const TileLds& L, int
         acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.z)), p.h_eps);
         acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.z)), p.h_eps);
     }
-    if (p.sdf != nullptr && (int)threadIdx.x < P) {
-        const int i = threadIdx.x;
-        const float u = p.shape[i][0], w = p.shape[i][1];
+    if (p.sdf != nullptr && i0 < P) {
+        const float u = p.shape[i0][0], w = p.shape[i0][1];
         const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
         const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
         acc_a += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pax, inv_res, offx), fmaf(pay, inv_res, offy)),
@@ -420,7 +436,7 @@ __device__ float2 fused_barrier_block2(const DevParams& p, const TileLds& L, int
         acc_b += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pbx, inv_res, offx), fmaf(pby, inv_res, offy)),
                              p.h_eps);
     }
-    return block_sum_f2<kRollWaves>(make_float2(acc_a, acc_b), L.slots);
+    return make_float2(acc_a, acc_b);
 }
 
 // Part of the fused barrier of one pose: every shape point against obstacles
@@ -513,7 +529,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // poses yet
     const int tc0 = min(tile_first_chunk(T), tc);
     const int nch = 1 + (T - tc0 + tc - 1) / tc;
-    const TileLds L = carve(smem, J, T, NS, tc * S);
+    const bool keep_noise = tile_keeps_noise(J, T, NS, S);
+    const TileLds L = carve(smem, J, T, NS, tc * S, keep_noise);
     const CtrlState* cs_in = p.st;
     const float S_e = cs_in->S_e;
     const uint64_t ctr = cs_in->counter;
@@ -539,11 +556,13 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         offx = (float)((ox - (double)p.map_x0) / (double)p.map_res - 0.5);
         offy = (float)((oy - (double)p.map_y0) / (double)p.map_res - 0.5);
     }
-    __syncthreads();
+    lds_barrier();
 
     // beta_0 = fused B(h(x0)); beta_d = fused B(h(x_d)), x_d = x_ref[T].
-    const float2 b0d = fused_barrier_block2(p, L, P, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1],
-                                            L.ref[T * NS + 2], inv_res, offx, offy);
+    const float2 b0d = block_sum_f2<kRollWaves>(
+        fused_barrier_share2(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
+                             inv_res, offx, offy),
+        L.slots);
     const float beta0 = b0d.x, beta_d = b0d.y;
 
     // ---- setup: lanes 0..S-1 own one sample each ----
@@ -569,14 +588,10 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // the common part c_t = gamma_B (c_{t-1} - beta_d) (c_0 = 0), whose sum is
     // -beta_d gamma_B/(1-gamma_B) (T - gamma_B (1-gamma_B^T)/(1-gamma_B)).
     // The common part's cost R_B sum_t c_t is the same for every sample and is
-    // added in FP64 (cshift), so a large beta_d cannot swamp the FP32 sums.
+    // added in FP64 (cshift), so a large beta_d cannot swamp the FP32 sums;
+    // one lane of the noise pool forms it during the second stage and leaves
+    // it in LDS.
     float beta = beta0;
-    double cshift;
-    {
-        const double g = (double)p.gamma_b;
-        const double geo = g * (1.0 - pow(g, (double)T)) / (1.0 - g);
-        cshift = (double)p.r_b * (-(double)beta_d * g / (1.0 - g) * ((double)T - geo));
-    }
     float S_hi = 0.0f, S_lo = 0.0f;
 
     float sa[PM], sb[PM];
@@ -589,6 +604,12 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     auto chunk_t0 = [&](int c) { return c == 0 ? 0 : tc0 + (c - 1) * tc; };
     auto chunk_len = [&](int c) { return c == 0 ? tc0 : min(tc, T - chunk_t0(c)); };
 
+    // the noise of sample kk at step t (Sec. IV-C mixture, scaled per Alg. 1)
+    auto noise_at = [&](int kk, int t) __attribute__((always_inline)) {
+        const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), p.seed_lo, p.seed_hi);
+        return nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
+    };
+
     // inputs of every (step, sample) of chunk c, over threads [first, block)
     auto inputs_chunk = [&](int c, int first) __attribute__((always_inline)) {
         const int t0 = chunk_t0(c), items = chunk_len(c) * S;
@@ -596,8 +617,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         for (int idx = tid - first; idx < items; idx += kRollBlock - first) {
             const int s = idx & (S - 1), t = t0 + idx / S;
             const int kk = tile * S + s;
-            const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), p.seed_lo, p.seed_hi);
-            const float2 z = nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
+            const float2 z = noise_at(kk, t);
             const float2 u = L.U[t];
             const float v0 = u.x + z.x, v1 = u.y + z.y;
             const float s0 = fminf(fmaxf(v0, p.u_min[0]), p.u_max[0]);
@@ -605,10 +625,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             float f0, f1;
             Model<MODEL>::inputs(p, s0, s1, f0, f1);
             dst[idx] = make_float4(f0, f1, cw0 * u.x * v0 + cw1 * u.y * v1, 0.0f);
-            if (kk < K) {
-                p.du[(size_t)(2 * t) * Kp + kk] = z.x;
-                p.du[(size_t)(2 * t + 1) * Kp + kk] = z.y;
-            }
+            if (keep_noise) L.nz[t * S + s] = z;
         }
     };
 
@@ -678,18 +695,26 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     };
 
     inputs_chunk(0, 0);
-    __syncthreads();
+    lds_barrier();
     for (int st_k = 0; st_k <= nch + 1; ++st_k) {
         if (tid == 0) L.work[(st_k + 1) & 1] = 0;      // counter of the next stage
         if (wave < DW) {
             if (owner && st_k >= 2) beta_chunk(st_k - 2);
             if (owner && st_k < nch) dynamics_chunk(st_k);
-        } else if (st_k + 1 < nch) {
-            inputs_chunk(st_k + 1, POOL0);
+        } else {
+            if (st_k + 1 < nch) inputs_chunk(st_k + 1, POOL0);
+            if (st_k == 1 && tid == POOL0) {
+                const double g = (double)p.gamma_b;
+                const double geo = g * (1.0 - pow(g, (double)T)) / (1.0 - g);
+                *reinterpret_cast<double*>(L.work + 2) =
+                    (double)p.r_b * (-(double)beta_d * g / (1.0 - g) * ((double)T - geo));
+            }
         }
         if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1, &L.work[st_k & 1]);
-        __syncthreads();
+        lds_barrier();
     }
+    // (the stage loop always runs stage 1, which wrote it)
+    const double cshift = *reinterpret_cast<const double*>(L.work + 2);
     if (owner) {
         const float* rf = L.ref + T * NS;
         float phi = 0.0f;
@@ -720,37 +745,66 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     if (use64) eta_b = block_sum_d<kRollWaves>(ek, L.slots);
     else eta_b = (double)block_sum_f<kRollWaves>((float)ek, L.slots);
 
-    // N_b[r] = sum over the tile's samples of e_k du[r][k]: TPR consecutive
-    // threads share a row, each summing every TPR-th sample in order, then
-    // combining across the TPR threads.
-    const int R = 2 * T;
-    int tpr = 1;
-    while (tpr < 64 && tpr * 2 * R <= kRollBlock) tpr *= 2;
-    const int rows_per_pass = kRollBlock / tpr;
-    const int part = tid & (tpr - 1);
+    // N_b[2t + c] = sum over the tile's samples of e_k du[t][c][k].  The
+    // noise is never stored in device memory on the way: it is kept in LDS
+    // when it fits and otherwise drawn again from its counter, bit-identical
+    // to the inputs phase (and written out here only when the controller
+    // exports it).  TPT consecutive threads share a step t, each
+    // summing every TPT-th sample in order, then combining across the TPT
+    // threads.
+    int tpt = 1;
+    while (tpt < 64 && (tpt << 1) * T <= kRollBlock) tpt <<= 1;
+    const int steps_per_pass = kRollBlock / tpt;
+    const int part = tid & (tpt - 1);
     const int k0 = tile * S;
     const int nk = min(S, K - k0);
-    for (int r0 = 0; r0 < R; r0 += rows_per_pass) {
-        const int r = r0 + tid / tpr;
-        double out;
+    const bool store_du = p.export_noise != 0;
+    for (int q0 = 0; q0 < T; q0 += steps_per_pass) {
+        const int t = q0 + tid / tpt;
+        double o0, o1;
         if (use64) {
-            double a = 0.0;
-            if (r < R) {
-                const float* row = p.du + (size_t)r * Kp + k0;
-                for (int s = part; s < nk; s += tpr) a += L.e[s] * (double)row[s];
+            double a0 = 0.0, a1 = 0.0;
+            if (t < T) {
+                for (int s = part; s < nk; s += tpt) {
+                    const float2 z = keep_noise ? L.nz[t * S + s] : noise_at(k0 + s, t);
+                    if (store_du) {
+                        p.du[(size_t)(2 * t) * Kp + k0 + s] = z.x;
+                        p.du[(size_t)(2 * t + 1) * Kp + k0 + s] = z.y;
+                    }
+                    a0 += L.e[s] * (double)z.x;
+                    a1 += L.e[s] * (double)z.y;
+                }
             }
-            for (int m = 1; m < tpr; m <<= 1) a += __shfl_xor(a, m);
-            out = a;
+            for (int m = 1; m < tpt; m <<= 1) {
+                a0 += __shfl_xor(a0, m);
+                a1 += __shfl_xor(a1, m);
+            }
+            o0 = a0;
+            o1 = a1;
         } else {
-            float a = 0.0f;
-            if (r < R) {
-                const float* row = p.du + (size_t)r * Kp + k0;
-                for (int s = part; s < nk; s += tpr) a = fmaf((float)L.e[s], row[s], a);
+            float a0 = 0.0f, a1 = 0.0f;
+            if (t < T) {
+                for (int s = part; s < nk; s += tpt) {
+                    const float2 z = keep_noise ? L.nz[t * S + s] : noise_at(k0 + s, t);
+                    if (store_du) {
+                        p.du[(size_t)(2 * t) * Kp + k0 + s] = z.x;
+                        p.du[(size_t)(2 * t + 1) * Kp + k0 + s] = z.y;
+                    }
+                    a0 = fmaf((float)L.e[s], z.x, a0);
+                    a1 = fmaf((float)L.e[s], z.y, a1);
+                }
             }
-            for (int m = 1; m < tpr; m <<= 1) a += __shfl_xor(a, m);
-            out = (double)a;
+            for (int m = 1; m < tpt; m <<= 1) {
+                a0 += __shfl_xor(a0, m);
+                a1 += __shfl_xor(a1, m);
+            }
+            o0 = (double)a0;
+            o1 = (double)a1;
         }
-        if (part == 0 && r < R) p.partN[(size_t)r * p.tiles + tile] = any ? out : 0.0;
+        if (part == 0 && t < T) {
+            p.partN[(size_t)(2 * t) * p.tiles + tile] = any ? o0 : 0.0;
+            p.partN[(size_t)(2 * t + 1) * p.tiles + tile] = any ? o1 : 0.0;
+        }
     }
     if (valid) {
         p.S[k] = S_hi;

@@ -162,7 +162,8 @@ std::string validate_config(const mppi_config* c)
     if (c->tile_samples != 0 && !tile_samples_supported(c->tile_samples))
         return "tile_samples must be 0, 16, 32, 64, 128 or 256";
     if (!(c->h_eps >= 1e-9f && c->h_eps <= 1e6f)) return "h_eps must lie in [1e-9, 1e6]";
-    for (int i = 0; i < 7; ++i)
+    if (c->export_noise != 0 && c->export_noise != 1) return "export_noise must be 0 or 1";
+    for (int i = 0; i < 6; ++i)
         if (c->reserved[i] != 0) return "reserved fields must be zero";
     return "";
 }
@@ -338,6 +339,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
         p.Qf[a] = a < n ? cfg->Qf[a] : 0.0f;
     }
     std::memcpy(p.shape, cfg->shape, sizeof p.shape);
+    p.export_noise = cfg->export_noise ? 1 : 0;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 
@@ -352,7 +354,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     p.U = static_cast<float*>(h->dalloc(sizeof(float) * 2 * T * kM, &st));
     p.Ustar = static_cast<float*>(h->dalloc(sizeof(float) * T * kM, &st));
     if (!external_scratch) {
-        p.du = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)T * kM * p.Kp, &st));
+        if (p.export_noise) p.du = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)T * kM * p.Kp, &st));
         p.S = static_cast<float*>(h->dalloc(sizeof(float) * 2 * (size_t)p.Kp, &st));
         p.e = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)p.Kp, &st));
     }
@@ -384,7 +386,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     e = hipMemset(p.U, 0, sizeof(float) * 2 * T * kM);
     if (e == hipSuccess) e = hipMemset(p.Ustar, 0, sizeof(float) * T * kM);
     if (!external_scratch) {
-        if (e == hipSuccess) e = hipMemset(p.du, 0, sizeof(float) * (size_t)T * kM * p.Kp);
+        if (e == hipSuccess && p.du) e = hipMemset(p.du, 0, sizeof(float) * (size_t)T * kM * p.Kp);
         if (e == hipSuccess) e = hipMemset(p.S, 0, sizeof(float) * 2 * (size_t)p.Kp);
         if (e == hipSuccess) e = hipMemset(p.e, 0, sizeof(float) * (size_t)p.Kp);
     }
@@ -673,6 +675,7 @@ extern "C" int mppi_get_noise(mppi_t* h, float* du)
 {
     CHECK_HANDLE(h);
     if (!du) return MPPI_E_INVALID;
+    if (!h->p.export_noise) return h->fail(MPPI_E_INVALID, "the noise is only kept with export_noise = 1");
     int s = h->sync();
     if (s) return s;
     const int K = h->cfg.K, T = h->cfg.T, Kp = h->p.Kp;

@@ -53,7 +53,7 @@ ScratchLayout scratch_layout(const DevParams& p)
         o += align256(n);
         return r;
     };
-    L.du = take(sizeof(float) * (size_t)p.T * kM * p.Kp);
+    L.du = take(p.export_noise ? sizeof(float) * (size_t)p.T * kM * p.Kp : 0);
     L.S = take(sizeof(float) * 2 * (size_t)p.Kp);
     L.e = take(sizeof(float) * (size_t)p.Kp);
     L.rho_b = take(sizeof(double) * (size_t)p.tiles);
@@ -203,7 +203,7 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
         DevParams q = h->p;
         char* base = d_arena + picks[i].offset;
         const ScratchLayout& L = rb.layout;
-        q.du = reinterpret_cast<float*>(base + L.du);
+        q.du = q.export_noise ? reinterpret_cast<float*>(base + L.du) : nullptr;
         q.S = reinterpret_cast<float*>(base + L.S);
         q.e = reinterpret_cast<float*>(base + L.e);
         q.rho_b = reinterpret_cast<double*>(base + L.rho_b);

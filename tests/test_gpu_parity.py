@@ -43,8 +43,11 @@ def _check_costs(Sg, Sr, sens, what=""):
 
 
 def _ctrl(wl, **over):
+    """A controller on the workload; the noise is exported (for the noise
+    checks) unless the caller says otherwise."""
     from paper_2504_06437_amd.controller import Controller
     p = dict(wl["params"])
+    p["export_noise"] = True
     p.update(over)
     c = Controller(p)
     c.load_workload(wl)
@@ -336,5 +339,23 @@ def test_async_device_step_matches_sync_step():
     np.testing.assert_array_equal(ua, got[0])
     np.testing.assert_array_equal(ua2, got[1])
     np.testing.assert_array_equal(a.controls(), b.controls())
+    a.close()
+    b.close()
+
+
+def test_noise_export_changes_nothing_else():
+    """Without export the noise is never stored (and cannot be read back);
+    every other output is bit-identical to the exporting controller's."""
+    from paper_2504_06437_amd import _lib as A
+    wl = W.car(K=1000, T=30, J=40)
+    a, _ = _ctrl(wl)
+    b, _ = _ctrl(wl, export_noise=False)
+    for _ in range(2):
+        np.testing.assert_array_equal(a.step(wl["x0"]), b.step(wl["x0"]))
+        np.testing.assert_array_equal(a.costs(), b.costs())
+        np.testing.assert_array_equal(a.weights(), b.weights())
+        np.testing.assert_array_equal(a.controls(), b.controls())
+    with pytest.raises(A.MppiError):
+        b.noise()
     a.close()
     b.close()

@@ -44,12 +44,13 @@ def _alone(wl):
 
 
 def _scratch_bound(p):
-    """Upper bound of one request's scratch bytes (tiles of the smallest size)."""
+    """Upper bound of one request's scratch bytes (tiles of the smallest
+    size; no exported noise)."""
     K, T = p["K"], p["T"]
     Kp = (K + 63) // 64 * 64
     tiles = (K + 15) // 16
     a = lambda b: (b + 255) // 256 * 256  # noqa: E731
-    return (a(4 * T * 2 * Kp) + a(8 * Kp) + a(4 * Kp) + 3 * a(8 * tiles) + a(4 * tiles) + a(16 * T * tiles))
+    return a(0) + a(8 * Kp) + a(4 * Kp) + 3 * a(8 * tiles) + a(4 * tiles) + a(16 * T * tiles)
 
 
 def _serve_and_compare(wls, reqs, **server_kw):
