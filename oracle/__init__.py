@@ -90,6 +90,8 @@ def lib():
         L.orc_fused_barrier.restype = ctypes.c_double
         L.orc_rollout_one.argtypes = [cp, wp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_rollout_one.restype = ctypes.c_double
+        L.orc_exploration.argtypes = [cp, wp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_exploration.restype = ctypes.c_double
         L.orc_clearance.argtypes = [cp, wp, dp]
         L.orc_clearance.restype = ctypes.c_double
         L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
@@ -250,6 +252,16 @@ def rollout_one(params: dict, world: World, x0, U, du_k, x_ref, S_e=1.0, beta_d=
     if with_clearance:
         return S, X, beta, mh.value, sens.value
     return S, X, beta
+
+
+def exploration(params: dict, world: World, x0, Ustar, beta_d: float, mu: float):
+    """(S_e, C_B): the next exploration rate mu ln(e + C_B) and the barrier
+    cost of the noise-free rollout of U* from x0 (Sec. IV-B)."""
+    cfg = make_cfg(params)
+    cb = ctypes.c_double()
+    se = lib().orc_exploration(ctypes.byref(cfg), ctypes.byref(world.s), _dp(_f64(x0)), _dp(_f64(Ustar)),
+                               float(beta_d), float(mu), ctypes.byref(cb))
+    return se, cb.value
 
 
 def clearance(params: dict, world: World, x) -> float:

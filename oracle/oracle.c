@@ -318,6 +318,31 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
     return S + phi;
 }
 
+/* Sec. IV-B, eq. scaling factor, evaluated as the closing loop of
+ * Algorithm 1 does: after the update, the augmented state is rolled out under
+ * U* alone (no noise; inputs saturated inside f), its barrier state follows
+ * eq. barrier_update from beta_0 = B(h(x0)), the barrier cost adds R_B beta_t
+ * for t = 1..T, and the next exploration rate is mu ln(e + C_B), e = exp(1).
+ * Reading: the paper takes the barrier state as positive; when beta_d makes
+ * C_B negative, the logarithm sees 0, so S_e >= mu. */
+double orc_exploration(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* Ustar,
+                       double beta_d, double mu, double* C_B_out)
+{
+    const int n = orc_state_dim(cfg->model);
+    double x[ORC_NMAX], xn[ORC_NMAX];
+    for (int a = 0; a < n; ++a) x[a] = x0[a];
+    double beta = orc_fused_barrier(cfg, w, x);
+    double C_B = 0.0;
+    for (int t = 0; t < cfg->T; ++t) {
+        orc_dynamics(cfg, x, Ustar + (size_t)t * ORC_M, xn);
+        for (int a = 0; a < n; ++a) x[a] = xn[a];
+        beta = orc_fused_barrier(cfg, w, x) - cfg->gamma_b * (beta_d - beta);
+        C_B += cfg->r_b * beta;
+    }
+    if (C_B_out) *C_B_out = C_B;
+    return mu * log(exp(1.0) + (C_B > 0.0 ? C_B : 0.0));
+}
+
 /* eq. control_update: rho = min_k S_k; e_k = exp(-(S_k - rho)/lambda);
  * w_k = e_k / sum e.  A non-finite cost gets weight 0; if no cost is finite
  * the iteration is numerically failed. */

@@ -110,6 +110,14 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
                        const double* U, const double* du_k, const double* x_ref,
                        double S_e, double beta_d, double* X, double* beta, double* min_h, double* sens);
 
+/* Adaptive exploration (Sec. IV-B eq. scaling factor; closing loop of
+ * Algorithm 1): the barrier cost C_B = sum_{t=1..T} R_B beta_t of the
+ * noise-free rollout of U* from x0, and the next exploration rate
+ * S_e = mu ln(e + C_B), returned.  C_B (optional output) is the raw sum; a
+ * negative C_B (possible when beta_d is large) enters the logarithm as 0. */
+double orc_exploration(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* Ustar,
+                       double beta_d, double mu, double* C_B);
+
 /* Min-shifted exponential weights.  Returns ORC_OK or ORC_NUMERIC. */
 int orc_weights(const double* S, int K, double lambda, double* w, double* rho, double* eta);
 

@@ -487,3 +487,46 @@ def test_all_costs_non_finite_is_a_numeric_failure(orc):
     r = _step(orc, wl)
     assert r["status"] == 4
     np.testing.assert_array_equal(r["Ustar"], wl["U0"])
+
+
+def test_exploration_rate_hover_closed_form(orc):
+    """Sec. IV-B eq. scaling factor on a hovering quadrotor: U* = 0 keeps the
+    body still, so the fused barrier b is constant -- here summed by hand from
+    the geometry -- and C_B = R_B sum_{t=1..T} beta_t follows the barrier-state
+    closed form; S_e = mu ln(e + C_B)."""
+    T, gamma, R_B, mu = 30, 0.5, 0.2, 0.4
+    p = _params("quad6", T=T, gamma_b=gamma, r_b=R_B)
+    obs = [[0.0, 1.5, 0.7], [2.0, 0.0, 0.4]]
+    world = orc.World(obs)
+    x0 = np.array([0.3, 0.2, 0.0, 0.0, 0.0, 0.0])
+    # shape points on the body axis at heading 0: (x + s_i, z), s_i = -0.2 + 0.4 i / 6
+    b = sum(1.0 / ((0.3 + (-0.2 + 0.4 * i / 6.0) - cx) ** 2 + (0.2 - cy) ** 2 - r * r)
+            for i in range(7) for cx, cy, r in obs)
+    beta_d = 0.8
+    star = (b - gamma * beta_d) / (1 - gamma)
+    C_B = R_B * (T * star + (b - star) * gamma * (1 - gamma ** T) / (1 - gamma))
+    se, cb = orc.exploration(p, world, x0, np.zeros((T, 2)), beta_d, mu)
+    assert abs(cb - C_B) < 1e-12 * abs(C_B)
+    assert abs(se - mu * math.log(math.e + C_B)) < 1e-14
+
+
+def test_exploration_rate_without_barrier_cost_is_mu(orc):
+    """C_B = 0 (no barrier weight, or no obstacles with beta_d = 0) gives
+    S_e = mu ln e = mu; a negative C_B (beta_d above the trajectory's barrier)
+    also gives mu; the rate grows with the barrier cost."""
+    T, mu = 20, 0.4
+    wl = W.quad_small(K=4, T=T)
+    world = orc.World.from_workload(wl)
+    U = np.full((T, 2), 0.3)
+    se, cb = orc.exploration(dict(wl["params"], r_b=0.0), world, wl["x0"], U, 0.5, mu)
+    assert cb == 0.0 and se == mu * math.log(math.e)
+    se, cb = orc.exploration(wl["params"], orc.World([]), wl["x0"], U, 0.0, mu)
+    assert cb == 0.0 and abs(se - mu) < 1e-15
+    se, cb = orc.exploration(wl["params"], world, wl["x0"], U, 1e6, mu)
+    assert cb < 0.0 and abs(se - mu) < 1e-15
+    # closer obstacles -> larger barrier cost -> larger exploration rate
+    near = orc.World([[1.0, 1.6, 0.3]])
+    far = orc.World([[1.0, 4.0, 0.3]])
+    se_near, cb_near = orc.exploration(wl["params"], near, wl["x0"], U, 0.0, mu)
+    se_far, cb_far = orc.exploration(wl["params"], far, wl["x0"], U, 0.0, mu)
+    assert cb_near > cb_far > 0.0 and se_near > se_far > mu
