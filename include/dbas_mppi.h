@@ -83,6 +83,12 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *  - export_noise: 0 (default) -- the noise lives only inside the rollout
  *    kernel and is never stored; 1 -- every iteration also writes it to
  *    device memory (K*T*8 bytes) so that mppi_get_noise can return it.
+ *  - adaptive_explore: 0 (default) -- S_e stays as mppi_set_exploration set
+ *    it (1 at creation); 1 -- after every iteration U* is rolled out once
+ *    without noise from x0, its barrier cost C_B = sum_{t=1..T} R_B beta_t
+ *    is formed, and the next iteration samples with
+ *    S_e = explore_mu ln(e + max(C_B, 0)) (Sec. IV-B eq. scaling factor and
+ *    the closing loop of Algorithm 1).  explore_mu in (0, 1), default 0.4.
  */
 typedef struct mppi_config {
     uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
@@ -102,7 +108,9 @@ typedef struct mppi_config {
     int32_t init_mode;             /* mppi_init_mode */
     int32_t tile_samples;          /* 0 = autotune */
     int32_t export_noise;          /* 1: also store each iteration's noise (mppi_get_noise) */
-    int32_t reserved[6];           /* must be zero */
+    int32_t adaptive_explore;      /* 1: S_e follows the barrier cost of U* (Sec. IV-B) */
+    float explore_mu;              /* coarseness factor mu in (0,1) of S_e = mu ln(e + C_B) */
+    int32_t reserved[4];           /* must be zero */
 } mppi_config;
 
 /* Where a handle runs.  stream: a hipStream_t owned by the caller (NULL: the
@@ -132,6 +140,8 @@ typedef struct mppi_step_info {
     float beta_d;                  /* fused barrier at x_d = x_ref[T] */
     int32_t tile_samples;          /* samples per rollout workgroup used */
     int32_t tiles;                 /* sample tiles per iteration */
+    float S_e;                     /* exploration rate the next iteration samples with */
+    float cost_b;                  /* C_B of the last U* (adaptive_explore only, else 0) */
 } mppi_step_info;
 
 typedef struct mppi_ctrl mppi_t;

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
         ("P", ctypes.c_int32), ("shape", (ctypes.c_float * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("normaliser", ctypes.c_int32), ("init_mode", ctypes.c_int32),
         ("tile_samples", ctypes.c_int32), ("export_noise", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("adaptive_explore", ctypes.c_int32), ("explore_mu", ctypes.c_float), ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -68,7 +68,8 @@ class State(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("counter", ctypes.c_uint64), ("status", ctypes.c_int32), ("fp64_tiles", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("eta", ctypes.c_double), ("beta0", ctypes.c_float),
-                ("beta_d", ctypes.c_float), ("tile_samples", ctypes.c_int32), ("tiles", ctypes.c_int32)]
+                ("beta_d", ctypes.c_float), ("tile_samples", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("S_e", ctypes.c_float), ("cost_b", ctypes.c_float)]
 
 
 class Profile(ctypes.Structure):

@@ -55,6 +55,8 @@ def make_config(params: dict) -> A.Config:
     c.init_mode = A.INIT_MODE[params.get("init_mode", "repeat")]
     c.tile_samples = int(params.get("tile_samples", 0))
     c.export_noise = int(bool(params.get("export_noise", False)))
+    c.adaptive_explore = int(bool(params.get("adaptive_explore", False)))
+    c.explore_mu = float(params.get("explore_mu", 0.4))
     return c
 
 

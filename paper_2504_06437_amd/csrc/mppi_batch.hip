@@ -142,11 +142,12 @@ struct mppi_batch {
     DevParams* d_params = nullptr;
     BatchUnit* d_units = nullptr;
     RowUnit* d_rows = nullptr;
+    int32_t* d_exp = nullptr;       // controllers with adaptive exploration
     uint32_t* d_queue = nullptr;
     BatchIn* d_in = nullptr;
     BatchIn* h_in = nullptr;        // pinned staging of the per-step states and buffer parities
-    int nunits = 0, nrows = 0, grid = 0;
-    size_t lds = 0;
+    int nunits = 0, nrows = 0, nexp = 0, grid = 0;
+    size_t lds = 0, lds_exp = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -157,7 +158,7 @@ struct mppi_batch {
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (void* p : {(void*)d_params, (void*)d_units, (void*)d_rows, (void*)d_queue, (void*)d_in})
+        for (void* p : {(void*)d_params, (void*)d_units, (void*)d_rows, (void*)d_exp, (void*)d_queue, (void*)d_in})
             if (p) (void)hipFree(p);
         if (h_in) (void)hipHostFree(h_in);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -184,7 +185,9 @@ struct mppi_batch {
         versions.resize(n);
         std::vector<std::pair<double, BatchUnit>> work;
         std::vector<RowUnit> rows;
+        std::vector<int32_t> exp_ids;
         size_t lds_max = 0;
+        lds_exp = 0;
         for (int c = 0; c < n; ++c) {
             params[c] = ctrls[c]->p;
             versions[c] = ctrls[c]->version;
@@ -194,18 +197,23 @@ struct mppi_batch {
             const double cost = (double)std::min(p.spt, p.K) * p.T * ((double)p.P * p.J + 64.0);
             for (int t = 0; t < p.tiles; ++t) work.push_back({cost, BatchUnit{c, t}});
             for (int r = 0; r < 2 * p.T; r += kUpdBlock / kWave) rows.push_back(RowUnit{c, r});
+            if (p.adaptive) {
+                exp_ids.push_back(c);
+                lds_exp = std::max(lds_exp, explore_lds_bytes(p.J, p.T));
+            }
         }
         std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         std::vector<BatchUnit> units(work.size());
         for (size_t i = 0; i < work.size(); ++i) units[i] = work[i].second;
         nunits = (int)units.size();
         nrows = (int)rows.size();
+        nexp = (int)exp_ids.size();
         lds = lds_max;
 
         int st;
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
         if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
-        for (void** p : {(void**)&d_params, (void**)&d_units, (void**)&d_rows})
+        for (void** p : {(void**)&d_params, (void**)&d_units, (void**)&d_rows, (void**)&d_exp})
             if (*p) { (void)hipFree(*p); *p = nullptr; }
         if ((st = hip(hipMalloc(&d_params, sizeof(DevParams) * n), "hipMalloc params"))) return st;
         if ((st = hip(hipMalloc(&d_units, sizeof(BatchUnit) * nunits), "hipMalloc units"))) return st;
@@ -213,16 +221,23 @@ struct mppi_batch {
         if ((st = hip(hipMemcpy(d_params, params.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice), "params"))) return st;
         if ((st = hip(hipMemcpy(d_units, units.data(), sizeof(BatchUnit) * nunits, hipMemcpyHostToDevice), "units"))) return st;
         if ((st = hip(hipMemcpy(d_rows, rows.data(), sizeof(RowUnit) * nrows, hipMemcpyHostToDevice), "rows"))) return st;
+        if (nexp) {
+            if ((st = hip(hipMalloc(&d_exp, sizeof(int32_t) * nexp), "hipMalloc explore list"))) return st;
+            if ((st = hip(hipMemcpy(d_exp, exp_ids.data(), sizeof(int32_t) * nexp, hipMemcpyHostToDevice), "explore list")))
+                return st;
+        }
 
         int cus = 0;
         if ((st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "CU count"))) return st;
         grid = std::max(1, std::min(nunits, cus * batch_rollout_blocks_per_cu(lds)));
 
-        // capture: per-step inputs H2D, persistent rollout, row update
+        // capture: per-step inputs H2D, persistent rollout, row update, and the
+        // exploration rate of the controllers that adapt it
         if ((st = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture"))) return st;
         hipError_t e = hipMemcpyAsync(d_in, h_in, sizeof(BatchIn) * n, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = launch_batch_rollout(d_params, d_units, nunits, d_in, d_queue, grid, lds, stream);
         if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, d_in, nullptr, stream);
+        if (e == hipSuccess && nexp) e = launch_batch_explore(d_params, d_exp, nexp, d_in, lds_exp, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip(e, "captured launch"); }

@@ -26,7 +26,7 @@ struct CtrlState {
     float S_e;               // exploration rate
     int32_t status;          // status of the last iteration
     float beta0, beta_d;     // fused barrier at x0 and at x_d
-    uint32_t reserved0;
+    float cost_b;            // C_B of the last U* (adaptive exploration)
     uint32_t iter;           // iterations run (the host tracks the same count)
     int32_t fp64_tiles;      // tiles of the last iteration whose weights ran in FP64
     int32_t pad;
@@ -54,6 +54,8 @@ struct DevParams {
     int32_t map_w, map_h;
     float map_x0, map_y0, map_res;
     int32_t export_noise;    // 1: the rollout also stores the noise into du
+    int32_t adaptive;        // 1: S_e follows the barrier cost of U*
+    float explore_mu;
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
     const float* xref;       // [T+1][n] world frame
@@ -150,6 +152,13 @@ __host__ __device__ inline bool tile_keeps_noise(int J, int T, int n, int S)
            kLdsLimit;
 }
 
+// Dynamic LDS bytes of the adaptive-exploration kernel: obstacles, the T+1
+// poses of the U* rollout, their fused barriers.
+inline size_t explore_lds_bytes(int J, int T)
+{
+    return (size_t)obstacle_slots(J) * 16 + (size_t)(T + 1) * 16 + (size_t)(T + 1) * 4;
+}
+
 // Dynamic LDS bytes one rollout tile of this controller needs.
 inline size_t tile_lds_bytes(int J, int T, int n, int S)
 {
@@ -164,6 +173,9 @@ hipError_t launch_batch_rollout(const DevParams* d_params, const BatchUnit* d_un
                                 const BatchIn* d_in, uint32_t* d_queue, int grid, size_t lds, hipStream_t s);
 hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, const BatchIn* d_in,
                                float* d_u0s, hipStream_t s);
+hipError_t launch_explore(const DevParams& p, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids, int n, const BatchIn* d_in,
+                                size_t lds, hipStream_t s);
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s);
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s);
 int batch_rollout_blocks_per_cu(size_t lds);

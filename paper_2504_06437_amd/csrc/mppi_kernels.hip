@@ -905,6 +905,101 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive exploration (Sec. IV-B eq. scaling factor; closing loop of
+// Algorithm 1), one workgroup per controller: U* is rolled out once without
+// noise from x0 (one lane; inputs saturated inside f), the fused barrier of
+// every pose is summed by one wave per pose, then one lane runs
+// eq. barrier_update from beta_0 in FP64, forms C_B = sum_{t=1..T} R_B beta_t
+// and sets the next iteration's S_e = mu ln(e + max(C_B, 0)).
+// ---------------------------------------------------------------------------
+constexpr int kExpBlock = 256;
+
+template <int MODEL>
+__device__ void explore_poses(const DevParams& p, const X0& xs, float4* pose)
+{
+    constexpr int NS = Model<MODEL>::NS;
+    float x[NS];
+    x[0] = 0.0f;
+    x[1] = 0.0f;
+#pragma unroll
+    for (int a = 2; a < NS; ++a) x[a] = xs.v[a];
+    float sth, cth;
+    heading_sincos(x[2], sth, cth);
+    pose[0] = make_float4(0.0f, 0.0f, cth, sth);
+    for (int t = 0; t < p.T; ++t) {
+        const float s0 = fminf(fmaxf(p.Ustar[2 * t], p.u_min[0]), p.u_max[0]);
+        const float s1 = fminf(fmaxf(p.Ustar[2 * t + 1], p.u_min[1]), p.u_max[1]);
+        float f0, f1;
+        Model<MODEL>::inputs(p, s0, s1, f0, f1);
+        Model<MODEL>::step(p, x, f0, f1, sth, cth);
+        heading_sincos(x[2], sth, cth);
+        pose[t + 1] = make_float4(x[0], x[1], cth, sth);
+    }
+}
+
+__device__ void explore_ctrl(const DevParams& p, const X0& xs, unsigned char* smem)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int T = p.T, J = p.J, P = p.P;
+    float4* obs = reinterpret_cast<float4*>(smem);
+    float4* pose = reinterpret_cast<float4*>(smem + (size_t)obstacle_slots(J) * 16);
+    float* bv = reinterpret_cast<float*>(smem + (size_t)obstacle_slots(J) * 16 + (size_t)(T + 1) * 16);
+    // the rollout's local frame, centred on the start position
+    const double ox = (double)xs.v[0], oy = (double)xs.v[1];
+    for (int j = tid; j < J; j += kExpBlock) {
+        const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
+        obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(-(r * r)), 0.0f);
+    }
+    float inv_res = 0.0f, offx = 0.0f, offy = 0.0f;
+    const bool has_map = p.sdf != nullptr;
+    if (has_map) {
+        inv_res = (float)(1.0 / (double)p.map_res);
+        offx = (float)((ox - (double)p.map_x0) / (double)p.map_res - 0.5);
+        offy = (float)((oy - (double)p.map_y0) / (double)p.map_res - 0.5);
+    }
+    if (tid == 0) {
+        switch (p.model) {
+        case MPPI_QUAD6: explore_poses<MPPI_QUAD6>(p, xs, pose); break;
+        case MPPI_QUAD5: explore_poses<MPPI_QUAD5>(p, xs, pose); break;
+        default: explore_poses<MPPI_CAR>(p, xs, pose); break;
+        }
+    }
+    __syncthreads();
+    for (int t = wave; t <= T; t += kExpBlock / kWave) {
+        const float4 q = pose[t];
+        float acc = 0.0f;
+        for (int idx = lane; idx < P * J; idx += kWave) {
+            const int i = idx / J, j = idx - i * J;
+            const float px = fmaf(p.shape[i][0], q.z, fmaf(-p.shape[i][1], q.w, q.x));
+            const float py = fmaf(p.shape[i][0], q.w, fmaf(p.shape[i][1], q.z, q.y));
+            const float4 o = obs[j];
+            const float dx = px - o.x, dy = py - o.y;
+            acc += barrier_rcp(fmaf(dx, dx, fmaf(dy, dy, o.z)), p.h_eps);
+        }
+        if (has_map && lane < P) {
+            const float px = fmaf(p.shape[lane][0], q.z, fmaf(-p.shape[lane][1], q.w, q.x));
+            const float py = fmaf(p.shape[lane][0], q.w, fmaf(p.shape[lane][1], q.z, q.y));
+            acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
+                               p.h_eps);
+        }
+        acc = wave_sum_f(acc);
+        if (lane == 0) bv[t] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        CtrlState* st = p.st;
+        const double g = (double)p.gamma_b, bd = (double)st->beta_d;
+        double beta = (double)bv[0], cb = 0.0;
+        for (int t = 1; t <= T; ++t) {
+            beta = (double)bv[t] - g * (bd - beta);
+            cb += (double)p.r_b * beta;
+        }
+        st->cost_b = (float)cb;
+        st->S_e = (float)((double)p.explore_mu * log(2.718281828459045 + fmax(cb, 0.0)));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 template <int MODEL, int S, int PT>
@@ -993,6 +1088,30 @@ __global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __r
     update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, sf, slots);
 }
 
+__global__ __launch_bounds__(kExpBlock) void k_explore(DevParams p, StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    X0 xs;
+#pragma unroll
+    for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0_ptr ? (i < p.n ? a.x0_ptr[i] : 0.0f) : a.x0[i];
+    xs.parity = a.parity;
+    explore_ctrl(p, xs, smem);
+}
+
+// One workgroup per listed controller of a batch.
+__global__ __launch_bounds__(kExpBlock) void k_batch_explore(const DevParams* __restrict__ ps,
+                                                             const int32_t* __restrict__ ids,
+                                                             const BatchIn* __restrict__ in)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = ids[blockIdx.x];
+    X0 xs;
+#pragma unroll
+    for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[c].x0[i];
+    xs.parity = in[c].parity;
+    explore_ctrl(ps[c], xs, smem);
+}
+
 // w_k = e_k f_b(k) / eta: the weights the update used.
 __global__ __launch_bounds__(256) void k_weights(DevParams p, double* w)
 {
@@ -1068,6 +1187,19 @@ hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units
                                float* d_u0s, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_update, dim3(nunits), dim3(kUpdBlock), 0, s, d_params, d_units, d_in, d_u0s);
+    return hipGetLastError();
+}
+
+hipError_t launch_explore(const DevParams& p, const StepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_explore, dim3(1), dim3(kExpBlock), explore_lds_bytes(p.J, p.T), s, p, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids, int n, const BatchIn* d_in,
+                                size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_explore, dim3(n), dim3(kExpBlock), lds, s, d_params, d_ids, d_in);
     return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ extern "C" int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_con
     c->normaliser = MPPI_NORM_AUTO;
     c->init_mode = MPPI_INIT_REPEAT;
     c->tile_samples = 0;
+    c->explore_mu = 0.4f;
     const int n = state_dim(model);
     for (int a = 0; a < n; ++a) c->Q[a] = a < 2 ? 1.0f : 0.1f;
     for (int a = 0; a < n; ++a) c->Qf[a] = 10.0f * c->Q[a];
@@ -163,7 +164,10 @@ std::string validate_config(const mppi_config* c)
         return "tile_samples must be 0, 16, 32, 64, 128 or 256";
     if (!(c->h_eps >= 1e-9f && c->h_eps <= 1e6f)) return "h_eps must lie in [1e-9, 1e6]";
     if (c->export_noise != 0 && c->export_noise != 1) return "export_noise must be 0 or 1";
-    for (int i = 0; i < 6; ++i)
+    if (c->adaptive_explore != 0 && c->adaptive_explore != 1) return "adaptive_explore must be 0 or 1";
+    if (c->adaptive_explore && !(c->explore_mu > 0.0f && c->explore_mu < 1.0f))
+        return "explore_mu must lie in (0, 1)";
+    for (int i = 0; i < 4; ++i)
         if (c->reserved[i] != 0) return "reserved fields must be zero";
     return "";
 }
@@ -340,6 +344,8 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     }
     std::memcpy(p.shape, cfg->shape, sizeof p.shape);
     p.export_noise = cfg->export_noise ? 1 : 0;
+    p.adaptive = cfg->adaptive_explore ? 1 : 0;
+    p.explore_mu = cfg->explore_mu;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 
@@ -548,6 +554,7 @@ int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_
     HIP_TRY(this, launch_rollout(p, a, stream));
     if (ev) HIP_TRY(this, hipEventRecord(ev[1], stream));
     HIP_TRY(this, launch_update(p, a, stream));
+    if (p.adaptive) HIP_TRY(this, launch_explore(p, a, stream));
     ++iter;
     if (ev) HIP_TRY(this, hipEventRecord(ev[2], stream));
     return MPPI_OK;
@@ -703,6 +710,8 @@ extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
     info->beta_d = st.beta_d;
     info->tile_samples = h->p.spt;
     info->tiles = h->p.tiles;
+    info->S_e = st.S_e;
+    info->cost_b = st.cost_b;
     return MPPI_OK;
 }
 

@@ -139,13 +139,13 @@ struct mppi_server {
     // Lays out the launch of `picks` in the slot's pinned staging; returns the
     // bytes to copy.  Called with the lock held.
     size_t stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows_out, size_t* off_in, size_t* off_rows,
-                 size_t* off_units);
+                 size_t* off_units, int* nexp_out, size_t* off_exp, size_t* lds_exp_out);
     void scheduler();
     void waiter(int si);
 };
 
 size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows_out, size_t* off_in,
-                          size_t* off_rows, size_t* off_units)
+                          size_t* off_rows, size_t* off_units, int* nexp_out, size_t* off_exp, size_t* lds_exp_out)
 {
     const auto& picks = sl.picks;
     const int n = (int)picks.size();
@@ -166,6 +166,8 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
     o += align256(sizeof(RowUnit) * nrows);
     *off_units = o;
     o += align256(sizeof(BatchUnit) * nunits);
+    *off_exp = o;
+    o += align256(sizeof(int32_t) * n);
     const size_t off_ref = o;
     o += align256(sizeof(float) * ref_floats);
     const size_t total = o;
@@ -191,6 +193,9 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
     auto* rows = reinterpret_cast<RowUnit*>(sl.h_stage + *off_rows);
     auto* units = reinterpret_cast<BatchUnit*>(sl.h_stage + *off_units);
     float* refs = reinterpret_cast<float*>(sl.h_stage + off_ref);
+    auto* exp_ids = reinterpret_cast<int32_t*>(sl.h_stage + *off_exp);
+    int nexp = 0;
+    size_t lds_exp = 0;
     size_t ref_at = 0;
     size_t lds = 0;
     std::vector<std::pair<double, BatchUnit>> work;
@@ -227,7 +232,13 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
         const double cost = (double)std::min(q.spt, q.K) * q.T * ((double)q.P * q.J + 64.0);
         for (int t = 0; t < q.tiles; ++t) work.push_back({cost, BatchUnit{i, t}});
         lds = std::max(lds, tile_lds_bytes(q.J, q.T, q.n, q.spt));
+        if (q.adaptive) {
+            exp_ids[nexp++] = i;
+            lds_exp = std::max(lds_exp, explore_lds_bytes(q.J, q.T));
+        }
     }
+    *nexp_out = nexp;
+    *lds_exp_out = lds_exp;
     std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     for (int u = 0; u < nunits; ++u) units[u] = work[u].second;
     *lds_out = lds;
@@ -254,9 +265,10 @@ void mppi_server::scheduler()
         seen = ~0ull;                       // look again at once: more may fit in another slot
         sl.busy = true;
         in_flight += (int)sl.picks.size();
-        size_t lds = 0, off_in = 0, off_rows = 0, off_units = 0;
-        int nunits = 0, nrows = 0;
-        const size_t bytes = stage(sl, &lds, &nunits, &nrows, &off_in, &off_rows, &off_units);
+        size_t lds = 0, off_in = 0, off_rows = 0, off_units = 0, off_exp = 0, lds_exp = 0;
+        int nunits = 0, nrows = 0, nexp = 0;
+        const size_t bytes =
+            stage(sl, &lds, &nunits, &nrows, &off_in, &off_rows, &off_units, &nexp, &off_exp, &lds_exp);
         ++stats.launches;
         batched_requests += (int64_t)sl.picks.size();
         lk.unlock();
@@ -271,6 +283,9 @@ void mppi_server::scheduler()
             e = launch_batch_rollout(d_params, d_units, nunits, d_in, sl.d_queue, grid, lds, sl.stream);
         }
         if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, d_in, nullptr, sl.stream);
+        if (e == hipSuccess && nexp)
+            e = launch_batch_explore(d_params, reinterpret_cast<const int32_t*>(sl.d_stage + off_exp), nexp, d_in,
+                                     lds_exp, sl.stream);
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
         if (e != hipSuccess) (void)hipGetLastError();
         lk.lock();
