@@ -8,8 +8,9 @@ arrays from the seeded generators in ``paper_2504_06437_amd.workloads`` (which
 hold no arithmetic of the method).
 
 The numerics live in ``oracle.c`` (plain C, FP64, libm); this module only
-marshals numpy arrays through ctypes.  See ``oracle.h`` for which passage of
-the paper each function follows.
+marshals numpy arrays through ctypes -- except the Savitzky-Golay smoothing of
+the update (``sgf``), written here in numpy from its definition.  See
+``oracle.h`` for which passage of the paper each C function follows.
 """
 from __future__ import annotations
 
@@ -296,8 +297,34 @@ def shift(params: dict, Ustar) -> np.ndarray:
     return out
 
 
+def sgf(y, half_window: int, order: int) -> np.ndarray:
+    """Savitzky-Golay smoothing (Algorithm 1's SGF) of y along its first axis,
+    from the definition: every output point is the value, at that point, of
+    the least-squares polynomial of degree `order` through the 2m+1 samples
+    of its window, m = half_window; near the ends the window is the first
+    (or last) 2m+1 samples, so the fitted polynomial is evaluated off-centre.
+    Each column is smoothed on its own.  m = 0 returns y unchanged."""
+    y = np.asarray(y, dtype=np.float64)
+    m = int(half_window)
+    if m == 0:
+        return y.copy()
+    n = y.shape[0]
+    W = 2 * m + 1
+    assert n >= W and 0 <= order < W
+    out = np.empty_like(y)
+    for t in range(n):
+        start = min(max(t - m, 0), n - W)
+        xs = np.arange(start, start + W, dtype=np.float64) - t
+        V = np.vander(xs, order + 1, increasing=True)
+        coef, *_ = np.linalg.lstsq(V, y[start:start + W], rcond=None)
+        out[t] = coef[0]            # the polynomial's value at x = 0, i.e. at t
+    return out
+
+
 def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int) -> dict:
-    """One full iteration; returns every intermediate as FP64 arrays."""
+    """One full iteration; returns every intermediate as FP64 arrays.  With
+    params["sgf_half_window"] = m > 0 the weighted increment is smoothed by
+    sgf(., m, params["sgf_order"]) before it is added to U (Algorithm 1)."""
     cfg = make_cfg(params)
     K, T = cfg.K, cfg.T
     x0, U, x_ref = _f64(x0), _f64(U), _f64(x_ref)
@@ -313,6 +340,12 @@ def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int) -> 
     st = lib().orc_step(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x0), _dp(U), _dp(x_ref),
                         float(S_e), int(counter), _dp(du), _dp(S), _dp(w), _dp(Ustar), _dp(Unext),
                         _dp(u0), *[ctypes.byref(s) for s in sc], _dp(clear), _dp(sens))
+    m = int(params.get("sgf_half_window", 0))
+    if m > 0 and st == OK:
+        inc = np.einsum("k,ktc->tc", w, du)
+        Ustar = U + sgf(inc, m, int(params.get("sgf_order", 2)))
+        Unext = shift(params, Ustar)
+        u0 = Ustar[0].copy()
     return {"status": st, "du": du, "S": S, "w": w, "Ustar": Ustar, "Unext": Unext, "u0": u0,
             "rho": sc[0].value, "eta": sc[1].value, "beta0": sc[2].value, "beta_d": sc[3].value,
             "clear": clear, "sens": sens}

@@ -530,3 +530,33 @@ def test_exploration_rate_without_barrier_cost_is_mu(orc):
     se_near, cb_near = orc.exploration(wl["params"], near, wl["x0"], U, 0.0, mu)
     se_far, cb_far = orc.exploration(wl["params"], far, wl["x0"], U, 0.0, mu)
     assert cb_near > cb_far > 0.0 and se_near > se_far > mu
+
+
+def test_savitzky_golay_textbook_coefficients(orc):
+    """Interior weights of the classical Savitzky-Golay tables: 5 points,
+    quadratic: (-3, 12, 17, 12, -3)/35; 7 points, cubic: (-2, 3, 6, 7, 6, 3, -2)/21
+    (the response to a unit impulse, which is symmetric)."""
+    y = np.zeros(21)
+    y[10] = 1.0
+    np.testing.assert_allclose(orc.sgf(y, 2, 2)[8:13], np.array([-3, 12, 17, 12, -3]) / 35.0, atol=1e-14)
+    np.testing.assert_allclose(orc.sgf(y, 3, 3)[7:14], np.array([-2, 3, 6, 7, 6, 3, -2]) / 21.0, atol=1e-14)
+    np.testing.assert_allclose(orc.sgf(y, 2, 2)[:8], 0.0, atol=1e-15)
+
+
+def test_savitzky_golay_reproduces_polynomials_up_to_its_order(orc):
+    """A polynomial of degree <= p passes unchanged, ends included (the end
+    windows fit the same polynomial); one of degree p + 1 does not; each
+    column is smoothed on its own; m = 0 and p = 2m are the identity."""
+    rng = np.random.default_rng(3)
+    t = np.arange(30, dtype=np.float64)
+    for m, p in ((2, 2), (3, 3), (4, 2), (5, 4)):
+        c = rng.standard_normal((p + 1, 2))
+        y = np.stack([np.polyval(c[::-1, j], t / 30.0) for j in range(2)], axis=1)
+        np.testing.assert_allclose(orc.sgf(y, m, p), y, rtol=0, atol=1e-11)
+        z = y + np.stack([(t / 30.0) ** (p + 1), np.zeros_like(t)], axis=1)
+        out = orc.sgf(z, m, p)
+        assert np.max(np.abs(out[:, 0] - z[:, 0])) > 1e-6
+        np.testing.assert_allclose(out[:, 1], y[:, 1], rtol=0, atol=1e-11)
+    y = rng.standard_normal((12, 2))
+    np.testing.assert_array_equal(orc.sgf(y, 0, 0), y)
+    np.testing.assert_allclose(orc.sgf(y, 2, 4), y, rtol=0, atol=1e-12)
