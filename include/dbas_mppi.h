@@ -89,6 +89,13 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *    is formed, and the next iteration samples with
  *    S_e = explore_mu ln(e + max(C_B, 0)) (Sec. IV-B eq. scaling factor and
  *    the closing loop of Algorithm 1).  explore_mu in (0, 1), default 0.4.
+ *  - sgf_half_window m, sgf_order p: Algorithm 1 smooths the weighted
+ *    increment sum_k w_k du_k along the horizon with a Savitzky-Golay filter
+ *    before adding it to U.  Every step t takes the value at t of the
+ *    least-squares polynomial of degree p through the 2m+1 steps of its
+ *    window; near the ends of the horizon the window is the first (last)
+ *    2m+1 steps.  m = 0 (default) applies no smoothing; m > 0 needs
+ *    T >= 2m+1, m <= 16 and 0 <= p <= min(2m, 8).
  */
 typedef struct mppi_config {
     uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
@@ -110,7 +117,9 @@ typedef struct mppi_config {
     int32_t export_noise;          /* 1: also store each iteration's noise (mppi_get_noise) */
     int32_t adaptive_explore;      /* 1: S_e follows the barrier cost of U* (Sec. IV-B) */
     float explore_mu;              /* coarseness factor mu in (0,1) of S_e = mu ln(e + C_B) */
-    int32_t reserved[4];           /* must be zero */
+    int32_t sgf_half_window;       /* Savitzky-Golay half window m (0: no smoothing) */
+    int32_t sgf_order;             /* Savitzky-Golay polynomial order p, 0 <= p <= min(2m, 8) */
+    int32_t reserved[2];           /* must be zero */
 } mppi_config;
 
 /* Where a handle runs.  stream: a hipStream_t owned by the caller (NULL: the

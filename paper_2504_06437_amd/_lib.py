@@ -52,7 +52,8 @@ class Config(ctypes.Structure):
         ("P", ctypes.c_int32), ("shape", (ctypes.c_float * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("normaliser", ctypes.c_int32), ("init_mode", ctypes.c_int32),
         ("tile_samples", ctypes.c_int32), ("export_noise", ctypes.c_int32),
-        ("adaptive_explore", ctypes.c_int32), ("explore_mu", ctypes.c_float), ("reserved", ctypes.c_int32 * 4),
+        ("adaptive_explore", ctypes.c_int32), ("explore_mu", ctypes.c_float),
+        ("sgf_half_window", ctypes.c_int32), ("sgf_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -57,6 +57,8 @@ def make_config(params: dict) -> A.Config:
     c.export_noise = int(bool(params.get("export_noise", False)))
     c.adaptive_explore = int(bool(params.get("adaptive_explore", False)))
     c.explore_mu = float(params.get("explore_mu", 0.4))
+    c.sgf_half_window = int(params.get("sgf_half_window", 0))
+    c.sgf_order = int(params.get("sgf_order", 2))
     return c
 
 

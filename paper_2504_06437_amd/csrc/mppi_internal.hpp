@@ -56,6 +56,9 @@ struct DevParams {
     int32_t export_noise;    // 1: the rollout also stores the noise into du
     int32_t adaptive;        // 1: S_e follows the barrier cost of U*
     float explore_mu;
+    int32_t sgf_m;           // Savitzky-Golay half window (0: no smoothing)
+    int32_t pad2;
+    const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
     const float* xref;       // [T+1][n] world frame

@@ -759,6 +759,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const int k0 = tile * S;
     const int nk = min(S, K - k0);
     const bool store_du = p.export_noise != 0;
+    // with smoothing, the unsmoothed sums gather in the (spent) chunk inputs
+    const bool smooth = p.sgf_m > 0;
+    double* nb = reinterpret_cast<double*>(L.in);
     for (int q0 = 0; q0 < T; q0 += steps_per_pass) {
         const int t = q0 + tid / tpt;
         double o0, o1;
@@ -802,8 +805,28 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             o1 = (double)a1;
         }
         if (part == 0 && t < T) {
-            p.partN[(size_t)(2 * t) * p.tiles + tile] = any ? o0 : 0.0;
-            p.partN[(size_t)(2 * t + 1) * p.tiles + tile] = any ? o1 : 0.0;
+            if (smooth) {
+                nb[2 * t] = o0;
+                nb[2 * t + 1] = o1;
+            } else {
+                p.partN[(size_t)(2 * t) * p.tiles + tile] = any ? o0 : 0.0;
+                p.partN[(size_t)(2 * t + 1) * p.tiles + tile] = any ? o1 : 0.0;
+            }
+        }
+    }
+    // Algorithm 1's Savitzky-Golay smoothing of the weighted increment is
+    // linear along the horizon, so it is applied to the tile's own sums:
+    // N_b[t][c] <- sum_j a_tj N_b[s_t + j][c] over the window of step t.
+    if (smooth) {
+        __syncthreads();
+        const int m = p.sgf_m, Wn = 2 * m + 1;
+        for (int r = tid; r < 2 * T; r += kRollBlock) {
+            const int t = r >> 1, c = r & 1;
+            const int s0 = min(max(t - m, 0), T - Wn);
+            const float* a = p.sgf_coef + (size_t)t * Wn;
+            double v = 0.0;
+            for (int j = 0; j < Wn; ++j) v += (double)a[j] * nb[2 * (s0 + j) + c];
+            p.partN[(size_t)r * p.tiles + tile] = any ? v : 0.0;
         }
     }
     if (valid) {

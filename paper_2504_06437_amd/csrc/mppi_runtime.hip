@@ -34,6 +34,54 @@ bool finite_all(const float* v, size_t n)
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// Savitzky-Golay weights for every step of a horizon of T: row t holds the
+// 2m+1 weights a_j with which the smoothed value at t is sum_j a_j y[s + j],
+// s = clamp(t - m, 0, T - 2m - 1): the value at t of the least-squares
+// polynomial of degree p through the window.  With V the window's Vandermonde
+// matrix (positions relative to t, scaled by 1/m) and V = QR by modified
+// Gram-Schmidt, the fit's value at t is e0^T R^-1 Q^T y, so a = Q z with
+// R^T z = e0.  FP64 throughout.
+std::vector<float> savitzky_golay_weights(int T, int m, int p)
+{
+    const int W = 2 * m + 1, C = p + 1;
+    std::vector<float> out((size_t)T * W);
+    std::vector<double> Q((size_t)W * C), R((size_t)C * C), z(C);
+    for (int t = 0; t < T; ++t) {
+        const int s = std::min(std::max(t - m, 0), T - W);
+        for (int j = 0; j < W; ++j) {
+            const double x = (double)(s + j - t) / (double)m;
+            double v = 1.0;
+            for (int k = 0; k < C; ++k, v *= x) Q[(size_t)j * C + k] = v;
+        }
+        std::fill(R.begin(), R.end(), 0.0);
+        for (int k = 0; k < C; ++k) {
+            for (int i = 0; i < k; ++i) {
+                double d = 0.0;
+                for (int j = 0; j < W; ++j) d += Q[(size_t)j * C + i] * Q[(size_t)j * C + k];
+                R[(size_t)i * C + k] = d;
+                for (int j = 0; j < W; ++j) Q[(size_t)j * C + k] -= d * Q[(size_t)j * C + i];
+            }
+            double nrm = 0.0;
+            for (int j = 0; j < W; ++j) nrm += Q[(size_t)j * C + k] * Q[(size_t)j * C + k];
+            nrm = std::sqrt(nrm);
+            R[(size_t)k * C + k] = nrm;
+            for (int j = 0; j < W; ++j) Q[(size_t)j * C + k] /= nrm;
+        }
+        // R^T z = e0 (forward substitution)
+        for (int k = 0; k < C; ++k) {
+            double v = k == 0 ? 1.0 : 0.0;
+            for (int i = 0; i < k; ++i) v -= R[(size_t)i * C + k] * z[i];
+            z[k] = v / R[(size_t)k * C + k];
+        }
+        for (int j = 0; j < W; ++j) {
+            double a = 0.0;
+            for (int k = 0; k < C; ++k) a += Q[(size_t)j * C + k] * z[k];
+            out[(size_t)t * W + j] = (float)a;
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 int mppi_ctrl::fail(int status, const char* fmt, ...)
@@ -95,6 +143,7 @@ extern "C" int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_con
     c->init_mode = MPPI_INIT_REPEAT;
     c->tile_samples = 0;
     c->explore_mu = 0.4f;
+    c->sgf_order = 2;
     const int n = state_dim(model);
     for (int a = 0; a < n; ++a) c->Q[a] = a < 2 ? 1.0f : 0.1f;
     for (int a = 0; a < n; ++a) c->Qf[a] = 10.0f * c->Q[a];
@@ -167,7 +216,13 @@ std::string validate_config(const mppi_config* c)
     if (c->adaptive_explore != 0 && c->adaptive_explore != 1) return "adaptive_explore must be 0 or 1";
     if (c->adaptive_explore && !(c->explore_mu > 0.0f && c->explore_mu < 1.0f))
         return "explore_mu must lie in (0, 1)";
-    for (int i = 0; i < 4; ++i)
+    if (c->sgf_half_window < 0 || c->sgf_half_window > 16) return "sgf_half_window must lie in 0..16";
+    if (c->sgf_half_window > 0) {
+        if (c->T < 2 * c->sgf_half_window + 1) return "smoothing needs T >= 2 sgf_half_window + 1";
+        if (c->sgf_order < 0 || c->sgf_order > 2 * c->sgf_half_window || c->sgf_order > 8)
+            return "sgf_order must lie in 0..min(2 sgf_half_window, 8)";
+    }
+    for (int i = 0; i < 2; ++i)
         if (c->reserved[i] != 0) return "reserved fields must be zero";
     return "";
 }
@@ -247,6 +302,9 @@ int mppi_ctrl::configure_tiles(int S)
     if (!tile_samples_supported(S) || tile_chunk_steps(p.J, cfg.T, p.n, S) == 0)
         return fail(MPPI_E_INVALID, "J=%d obstacles with T=%d do not fit the rollout's LDS budget at %d samples per tile",
                     p.J, cfg.T, S);
+    // the tile smooths its 2T partial sums (FP64) in the space of its chunk inputs
+    if (p.sgf_m > 0 && (size_t)2 * cfg.T * 8 > (size_t)2 * tile_chunk_steps(p.J, cfg.T, p.n, S) * S * 16)
+        return fail(MPPI_E_INVALID, "T=%d is too long to smooth within the LDS of a %d-sample tile", cfg.T, S);
     p.spt = S;
     p.tiles = (cfg.K + S - 1) / S;
     if (p.tiles > kMaxTiles) return fail(MPPI_E_INVALID, "K=%d needs more than %d tiles of %d samples", cfg.K, kMaxTiles, S);
@@ -346,6 +404,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     p.export_noise = cfg->export_noise ? 1 : 0;
     p.adaptive = cfg->adaptive_explore ? 1 : 0;
     p.explore_mu = cfg->explore_mu;
+    p.sgf_m = cfg->sgf_half_window;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 
@@ -366,6 +425,15 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     }
     p.xref = static_cast<float*>(h->dalloc(sizeof(float) * (size_t)(T + 1) * n, &st));
     p.st = static_cast<CtrlState*>(h->dalloc(sizeof(CtrlState), &st));
+    if (p.sgf_m > 0 && !st) {
+        const std::vector<float> coef = savitzky_golay_weights(T, p.sgf_m, cfg->sgf_order);
+        float* d = static_cast<float*>(h->dalloc(sizeof(float) * coef.size(), &st));
+        if (!st && hipMemcpy(d, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            st = h->fail(MPPI_E_DEVICE, "uploading the smoothing weights failed");
+        }
+        p.sgf_coef = d;
+    }
     if (st) {
         set_global_error(h->err);
         delete h;

@@ -39,7 +39,7 @@ def test_config_defaults_and_struct_layout():
         assert L.mppi_config_default(model, 1024, 30, ctypes.byref(c)) == A.OK
         assert c.abi_version == A.ABI_VERSION and c.K == 1024 and c.T == 30 and c.P == P
         assert abs(c.u_max[0] - lim) < 1e-6 and c.lam == 1.0 and abs(c.h_eps - 1e-4) < 1e-10
-        assert c.tile_samples == 0 and c.export_noise == 0 and list(c.reserved) == [0] * 4
+        assert c.tile_samples == 0 and c.export_noise == 0 and list(c.reserved) == [0] * 2
         assert c.adaptive_explore == 0 and abs(c.explore_mu - 0.4) < 1e-7
     assert L.mppi_config_default(7, 1, 1, ctypes.byref(A.Config())) == A.E_INVALID
     assert L.mppi_status_string(A.E_NUMERIC) == b"MPPI_E_NUMERIC"
