@@ -11,7 +11,8 @@ timed region: W untimed iterations, then `--steps` iterations issued back to
 back on the controller's stream with the states already in device memory,
 bracketed by device synchronisation.  Also reported:
   * roofline of the rollout kernel (algorithmic FLOPs per launch / its mean
-    duration from HIP events recorded on its stream during the timed region),
+    duration from HIP events recorded on its stream around every 8th launch
+    of the timed region),
   * p50/p99 control-step latency of the plain path (host state in, u0 out),
   * the batched path: 64 mixed controllers in one graph-captured persistent
     launch vs the same 64 stepped one after another through the plain path,
@@ -37,6 +38,10 @@ from paper_2504_06437_amd import workloads as W  # noqa: E402
 PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "rollout-steps/sec (K·T) and p50/p99 control-step latency, batched vs plain"
+# kernel durations come from HIP events around every PROFILE_EVERY-th
+# iteration of the timed loop (events around every iteration would add a few
+# microseconds to each step)
+PROFILE_EVERY = 8
 
 
 def rollout_flops_per_step(params: dict, J: int, with_map: bool) -> float:
@@ -99,7 +104,7 @@ def bench_plain(wl, steps, warmup):
     for i in range(warmup):
         c.step_async(x_dev.at(i % n_states), u_dev.at(i % n_states))
     assert c.synchronize() == 0
-    c.profile(True)
+    c.profile(PROFILE_EVERY)
     ev0, ev1 = hip.Event(), hip.Event()
     hip.synchronize()
     t0 = time.perf_counter()
@@ -387,7 +392,7 @@ def main():
                      "traffic": load_traffic("rollout", workload),
                      "kernel": "rollout", "kernel_ms_mean": r["rollout_ms_mean"],
                      "update_kernel_ms_mean": r["update_ms_mean"], "flops_per_launch": flops,
-                     "launches_timed": r["profiled"]},
+                     "launches_timed": r["profiled"], "timed_every": PROFILE_EVERY},
         "latency_ms": {"plain_p50": r["latency_ms"]["p50"], "plain_p99": r["latency_ms"]["p99"],
                        "n": r["latency_ms"]["n"], "note": "host state in, u0 out (PCIe-inclusive)"},
         "timing": {"wall_s": r["wall_s"], "event_ms": r["event_ms"]},

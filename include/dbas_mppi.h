@@ -227,8 +227,12 @@ const char* mppi_status_string(int32_t status);
 /* The stream (hipStream_t) a handle launches on. */
 void* mppi_stream(const mppi_t* h);
 
-/* Kernel timing.  With profiling on, every later iteration records HIP events
- * on the handle's stream around its rollout kernel and its update kernel.
+/* Kernel timing.  mppi_profile_enable(h, every): with every = n > 0, every
+ * n-th later iteration (the first one included) records HIP events on the
+ * handle's stream around its rollout kernel and its update kernel (the
+ * events themselves cost a few microseconds per recorded iteration, so a
+ * period above 1 keeps timed loops close to their unprofiled speed);
+ * every = 0 turns it off.
  * mppi_profile_read waits for the stream, returns the totals over the
  * iterations recorded since the last read, and clears them.  Turning it on
  * allocates events (up to 4096 iterations are kept; later ones are dropped
@@ -240,7 +244,7 @@ typedef struct mppi_profile {
     double update_ms;              /* summed update-kernel durations */
 } mppi_profile;
 
-int mppi_profile_enable(mppi_t* h, int32_t on);
+int mppi_profile_enable(mppi_t* h, int32_t every);
 int mppi_profile_read(mppi_t* h, mppi_profile* out);
 
 /* ------------------------------------------------------------------------ */

@@ -156,8 +156,10 @@ class Controller:
         return self.L.mppi_stream(self.h) or 0
 
     # -- kernel timing --
-    def profile(self, on: bool = True):
-        self._check(self.L.mppi_profile_enable(self.h, 1 if on else 0), "mppi_profile_enable")
+    def profile(self, every=1):
+        """Time the kernels of every `every`-th iteration (True = 1); 0 or
+        False turns kernel timing off."""
+        self._check(self.L.mppi_profile_enable(self.h, int(every)), "mppi_profile_enable")
 
     def profile_read(self) -> dict:
         pr = A.Profile()

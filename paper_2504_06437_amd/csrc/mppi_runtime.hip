@@ -614,7 +614,7 @@ int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_
     a.parity = iter & 1u;
     HIP_TRY(this, hipSetDevice(device));
     hipEvent_t* ev = nullptr;
-    if (profiling) {
+    if (profiling && prof_seen++ % prof_every == 0) {
         if (prof_used * 3 < (int)prof_events.size()) ev = &prof_events[(size_t)prof_used++ * 3];
         else ++prof_dropped;
     }
@@ -628,15 +628,19 @@ int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_
     return MPPI_OK;
 }
 
-extern "C" int mppi_profile_enable(mppi_t* h, int32_t on)
+extern "C" int mppi_profile_enable(mppi_t* h, int32_t every)
 {
     CHECK_HANDLE(h);
+    if (every < 0) return h->fail(MPPI_E_INVALID, "profiling period must be >= 0");
+    const bool on = every > 0;
     if (on && h->prof_events.empty()) {
         HIP_TRY(h, hipSetDevice(h->device));
         h->prof_events.resize(3 * 4096, nullptr);
         for (auto& e : h->prof_events) HIP_TRY(h, hipEventCreate(&e));
     }
-    h->profiling = on != 0;
+    h->profiling = on;
+    h->prof_every = on ? every : 1;
+    h->prof_seen = 0;
     h->prof_used = 0;
     h->prof_dropped = 0;
     return MPPI_OK;

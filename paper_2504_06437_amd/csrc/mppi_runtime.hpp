@@ -28,6 +28,8 @@ struct mppi_ctrl {
     dbas::HostResult* h_res = nullptr;
     // kernel timing (mppi_profile_*): event triples per recorded iteration
     bool profiling = false;
+    int prof_every = 1;                    // record every n-th iteration
+    int64_t prof_seen = 0;                 // iterations since profiling was turned on
     std::vector<hipEvent_t> prof_events;   // 3 per slot
     int prof_used = 0;
     int64_t prof_dropped = 0;
