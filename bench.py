@@ -14,6 +14,7 @@ bracketed by device synchronisation.  Also reported:
     duration from HIP events recorded on its stream around every 8th launch
     of the timed region),
   * p50/p99 control-step latency of the plain path (host state in, u0 out),
+  * the quadrotor at scale (K=16384, T=100, 400 obstacles + costmap),
   * the batched path: 64 mixed controllers in one graph-captured persistent
     launch vs the same 64 stepped one after another through the plain path,
   * the served path: 256 robots sending Poisson 50 Hz request streams to the
@@ -128,6 +129,42 @@ def bench_plain(wl, steps, warmup):
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99), "n": len(lat)},
         "tile_samples": info["tile_samples"], "tiles": info["tiles"],
     }
+
+
+def bench_at_scale(steps=20, warmup=3):
+    """The quadrotor at scale: K=16384, T=100, 400 obstacles + 512x512
+    costmap, FP64 normaliser.  Steps issued back to back from device-resident
+    states; rollout-kernel time from HIP events around every launch of this
+    short loop (events cost ~1% of an 0.8 ms kernel)."""
+    from paper_2504_06437_amd import hip
+    wl = W.quad_large()
+    p = wl["params"]
+    c = make_controller(wl)
+    x_dev = hip.DeviceArray.from_numpy(np.stack([wl["x0"]] * 4))
+    u_dev = hip.DeviceArray((4, 2))
+    for i in range(warmup):
+        c.step_async(x_dev.at(i % 4), u_dev.at(i % 4))
+    assert c.synchronize() == 0
+    c.profile(1)
+    hip.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        c.step_async(x_dev.at(i % 4), u_dev.at(i % 4))
+    status = c.synchronize()
+    wall = time.perf_counter() - t0
+    prof = c.profile_read()
+    info = c.info()
+    c.close()
+    assert status == 0, status
+    J = len(wl["obstacles"])
+    kernel_ms = prof["rollout_ms"] / max(prof["iterations"], 1)
+    flops = p["K"] * p["T"] * rollout_flops_per_step(p, J, True)
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    return {"workload": f"quadrotor K={p['K']} T={p['T']} J={J} P={len(p['shape'])} + 512x512 costmap",
+            "rollout_steps_per_s": p["K"] * p["T"] * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "rollout_kernel_ms_mean": kernel_ms, "update_kernel_ms_mean": prof["update_ms"] / max(prof["iterations"], 1),
+            "achieved_tflops": achieved, "frac_of_fp32_peak": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "tile_samples": info["tile_samples"], "fp64_tiles": info["fp64_tiles"], "steps": steps}
 
 
 def bench_batched(n_ctrl=64, steps=30, seed=3):
@@ -350,6 +387,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
@@ -397,6 +435,9 @@ def main():
                        "n": r["latency_ms"]["n"], "note": "host state in, u0 out (PCIe-inclusive)"},
         "timing": {"wall_s": r["wall_s"], "event_ms": r["event_ms"]},
     }
+    if not args.no_scale:
+        print("[bench] quadrotor at scale", file=sys.stderr, flush=True)
+        out["at_scale"] = bench_at_scale()
     if not args.no_batched:
         print("[bench] batched path: 64 mixed controllers", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
