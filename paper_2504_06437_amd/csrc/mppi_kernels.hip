@@ -441,40 +441,39 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 
 // Part of the fused barrier of one pose: every shape point against obstacles
 // j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus the costmap terms
-// when `with_map`.
+// when `with_map`.  With e = pose - o and d_i the rotated offset of point i,
+// h_i = |e + d_i|^2 - r^2 = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2: the first term
+// is shared by the P points of an obstacle and |d_i|^2 = |s_i|^2 is fixed,
+// so a pair costs one add and two FMAs.  (sa2, sb2) = 2 s_i, ss = |s_i|^2.
 template <int PT>
-__device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa,
-                                                    const float* sb, float4 pose, int j0, int js, bool with_map,
-                                                    float inv_res, float offx, float offy)
+__device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
+                                                    const float* sb2, const float* ss, float4 pose, int j0, int js,
+                                                    bool with_map, float inv_res, float offx, float offy)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
     const float eps = p.h_eps;
-    float px[PM], py[PM];
+    float tx[PM], ty[PM];       // 2 d_i
 #pragma unroll
     for (int i = 0; i < PM; ++i) {
-        px[i] = fmaf(sa[i], pose.z, fmaf(-sb[i], pose.w, pose.x));
-        py[i] = fmaf(sa[i], pose.w, fmaf(sb[i], pose.z, pose.y));
+        tx[i] = fmaf(sa2[i], pose.z, -sb2[i] * pose.w);
+        ty[i] = fmaf(sa2[i], pose.w, sb2[i] * pose.z);
     }
     float acc = 0.0f, acc2 = 0.0f;
     const int J = p.J;
 #pragma unroll 2
     for (int j = j0; j < J; j += js) {
         const float4 o = L.obs[j];
+        const float ex = pose.x - o.x, ey = pose.y - o.y;
+        const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
         if constexpr (PT != 0) {
             float h[PM];
 #pragma unroll
-            for (int i = 0; i < PM; ++i) {
-                const float dx = px[i] - o.x, dy = py[i] - o.y;
-                h[i] = clamp_h(fmaf(dx, dx, fmaf(dy, dy, o.z)), eps);
-            }
+            for (int i = 0; i < PM; ++i) h[i] = clamp_h(fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])), eps);
             reciprocal_sum<PM>(h, acc, acc2);
         } else {
 #pragma unroll
             for (int i = 0; i < PM; ++i) {
-                if (i < P) {
-                    const float dx = px[i] - o.x, dy = py[i] - o.y;
-                    acc += __builtin_amdgcn_rcpf(clamp_h(fmaf(dx, dx, fmaf(dy, dy, o.z)), eps));
-                }
+                if (i < P) acc += __builtin_amdgcn_rcpf(clamp_h(fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])), eps));
             }
         }
     }
@@ -483,8 +482,8 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 #pragma unroll
         for (int i = 0; i < PM; ++i) {
             if (PT || i < P) {
-                acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px[i], inv_res, offx),
-                                              fmaf(py[i], inv_res, offy)),
+                const float px = fmaf(0.5f, tx[i], pose.x), py = fmaf(0.5f, ty[i], pose.y);
+                acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
                                    eps);
             }
         }
@@ -594,11 +593,14 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     float beta = beta0;
     float S_hi = 0.0f, S_lo = 0.0f;
 
-    float sa[PM], sb[PM];
+    float sa2[PM], sb2[PM], ss[PM];       // 2 s_i and |s_i|^2
 #pragma unroll
     for (int i = 0; i < PM; ++i) {
-        sa[i] = (PT || i < P) ? p.shape[i][0] : 0.0f;
-        sb[i] = (PT || i < P) ? p.shape[i][1] : 0.0f;
+        const float a = (PT || i < P) ? p.shape[i][0] : 0.0f;
+        const float b = (PT || i < P) ? p.shape[i][1] : 0.0f;
+        sa2[i] = 2.0f * a;
+        sb2[i] = 2.0f * b;
+        ss[i] = fmaf(a, a, b * b);
     }
 
     auto chunk_t0 = [&](int c) { return c == 0 ? 0 : tc0 + (c - 1) * tc; };
@@ -687,7 +689,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = 0.0f;
             if (item < items)
-                part = fused_barrier_pose<PT>(p, L, P, sa, sb, pz[item], sp, nsp, has_map && sp == 0, inv_res, offx,
+                part = fused_barrier_pose<PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map && sp == 0, inv_res, offx,
                                               offy);
             for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             if (sp == 0 && item < items) bv[item] = part;
