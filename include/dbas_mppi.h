@@ -8,9 +8,11 @@
  * every sample while accumulating the cost-to-go (Sec. IV-A, eq.
  * cost-to-go_bas; Algorithm 1), form the min-shifted exponential weights and
  * the weighted-average update of the control sequence (Sec. III-A, eq.
- * control_update), hand u0* out and shift the warm start (Algorithm 1, closing
- * loop).  The adaptive exploration rate S_e (Sec. IV-B, eq. scaling factor) is
- * an input.
+ * control_update), optionally smoothed along the horizon (Algorithm 1's
+ * Savitzky-Golay filter), hand u0* out and shift the warm start (Algorithm 1,
+ * closing loop).  The exploration rate S_e (Sec. IV-B) is either set by the
+ * caller or, with adaptive_explore, recomputed after every iteration from the
+ * barrier cost of U* (eq. scaling factor).
  *
  * Conventions for every call:
  *  - Plain C types only.  Pointers are host pointers unless the argument says
@@ -187,7 +189,8 @@ int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float y0, float 
 int mppi_set_reference(mppi_t* h, const float* x_ref, int32_t mem);
 
 /* Exploration rate S_e > 0 (Sec. IV-B); it scales the noise variance and
- * divides the control cost. */
+ * divides the control cost.  With adaptive_explore every iteration replaces
+ * it for the next one; this call sets the rate the next iteration uses. */
 int mppi_set_exploration(mppi_t* h, float S_e);
 
 /* Overwrite the warm start U[T][2]. */
@@ -291,6 +294,10 @@ typedef struct mppi_server_stats {
 } mppi_server_stats;
 
 int mppi_server_create(const mppi_server_config* cfg, mppi_server_t** out);
+/* Stops the scheduler, waits for the launches in flight and frees everything.
+ * Requests still queued are dropped; no other call on `s` may be running or
+ * follow.  The server keeps each completed request until it is polled or
+ * waited for. */
 void mppi_server_destroy(mppi_server_t* s);
 /* Register a robot.  The configuration, obstacles and costmap are copied into
  * server-owned device state.  id receives the robot index. */
