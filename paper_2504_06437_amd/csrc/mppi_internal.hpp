@@ -32,12 +32,16 @@ struct CtrlState {
     int32_t pad;
 };
 
-// Written by the update kernel into pinned host memory.
+// Written by the update kernel into pinned host memory.  When the launch asks
+// for it (StepArgs::mark), seq (the number of iterations completed) is
+// written last, after system-scope fences, so a host thread that sees it
+// change may read u0 and status.
 struct HostResult {
     float u0[kM];
     int32_t status;
     int32_t pad;
     uint64_t counter;
+    uint64_t seq;
 };
 
 // Everything a kernel needs to run one controller's iteration.  Passed by
@@ -82,6 +86,8 @@ struct StepArgs {
     const float* x0_ptr;     // device x0 (overrides x0[] when non-null)
     float* u0_dev;           // optional device u0 output
     uint32_t parity;         // iterations run & 1: the half of U that holds the warm start
+    uint32_t mark;           // 1: publish u0, status and the completion mark to the host
+                             //    at once (system-scope fences), for a host thread spinning
 };
 
 // Per-step input of one controller of a batch (staged by the host).

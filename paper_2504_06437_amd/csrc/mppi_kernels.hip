@@ -381,6 +381,7 @@ struct X0 {
 };
 
 constexpr int kRollWaves = kRollBlock / kWave;
+constexpr int kSimdsPerCU = 4;
 constexpr int kUpdWaves = kUpdBlock / kWave;
 
 // Sum of a float pair over the block (NW waves); every thread gets it.
@@ -440,8 +441,8 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 }
 
 // Part of the fused barrier of one pose: every shape point against obstacles
-// j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus the costmap terms
-// when `with_map`.  With e = pose - o and d_i the rotated offset of point i,
+// j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus, with a costmap,
+// the costmap terms of shape points j0, j0 + js, ... below P.  With e = pose - o and d_i the rotated offset of point i,
 // h_i = |e + d_i|^2 - r^2 = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2: the first term
 // is shared by the P points of an obstacle and |d_i|^2 = |s_i|^2 is fixed,
 // so a pair costs one add and two FMAs.  (sa2, sb2) = 2 s_i, ss = |s_i|^2.
@@ -481,7 +482,7 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
     if (with_map) {
 #pragma unroll
         for (int i = 0; i < PM; ++i) {
-            if (PT || i < P) {
+            if ((PT || i < P) && i % js == j0) {
                 const float px = fmaf(0.5f, tx[i], pose.x), py = fmaf(0.5f, ty[i], pose.y);
                 acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
                                    eps);
@@ -674,8 +675,34 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // taken from the work counter
     auto barrier_chunk = [&](int c, int* counter) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
+        // split: among the splits that give every wave of the noise pool a
+        // unit, the one whose units, spread over the CU's SIMDs, cost least:
+        // ceil(units / SIMDs) units, each of ceil(J / nsp) obstacles x P
+        // pairs plus a fixed part (pose, shape transform, reduction: about 8
+        // pairs' worth).  Without such a split, the finest one.
         int lg = 0;
-        while (lg < 6 && (items << lg) < 48 * kWave && J >= (8 << lg)) ++lg;
+        {
+            long best = -1;
+            for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
+                const long units = ((long)(items << l) + kWave - 1) / kWave;
+                lg = l;                                  // the finest so far
+                if (units < kRollWaves - DW) continue;
+                const long per_lane = (J + (1 << l) - 1) >> l;
+                const long cost = (units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8);
+                if (best < 0 || cost < best) best = cost;
+            }
+            if (best >= 0) {
+                for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
+                    const long units = ((long)(items << l) + kWave - 1) / kWave;
+                    if (units < kRollWaves - DW) continue;
+                    const long per_lane = (J + (1 << l) - 1) >> l;
+                    if ((units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8) == best) {
+                        lg = l;
+                        break;
+                    }
+                }
+            }
+        }
         const int nsp = 1 << lg;
         const int units = ((items << lg) + kWave - 1) / kWave;
         const float4* pz = L.pose + (c & 1) * L.cs;
@@ -689,7 +716,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = 0.0f;
             if (item < items)
-                part = fused_barrier_pose<PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map && sp == 0, inv_res, offx,
+                part = fused_barrier_pose<PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map, inv_res, offx,
                                               offy);
             for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             if (sp == 0 && item < items) bv[item] = part;
@@ -859,7 +886,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 // loop) into the other half of the double buffer and u0*; the workgroup of
 // row 0 also records the iteration in the controller's state.
 // ---------------------------------------------------------------------------
-__device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, double* sf, double* slots)
+__device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, bool mark, double* sf,
+                            double* slots)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -908,23 +936,35 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
             }
             if (t == 0) {
                 if (u0_dev) u0_dev[r] = us;
-                if (p.res) p.res->u0[r] = us;
+                if (p.res) {
+                    p.res->u0[r] = us;
+                    if (mark) __threadfence_system();   // before the completion mark below
+                }
             }
         }
     }
-    if (first && tid == 0) {
-        const uint64_t c = st->counter;
-        const int status = ok ? MPPI_OK : MPPI_E_NUMERIC;
-        st->last_counter = c;
-        if (ok) st->counter = c + 1u;
-        st->rho = rho;
-        st->eta = eta;
-        st->status = status;
-        st->fp64_tiles = (int32_t)n64s;
-        st->iter += 1u;
-        if (p.res) {
-            p.res->status = status;
-            p.res->counter = c;
+    if (first) {
+        __syncthreads();                        // rows 0 and 1 (u0) are written by this workgroup
+        if (tid == 0) {
+            const uint64_t c = st->counter;
+            const int status = ok ? MPPI_OK : MPPI_E_NUMERIC;
+            st->last_counter = c;
+            if (ok) st->counter = c + 1u;
+            st->rho = rho;
+            st->eta = eta;
+            st->status = status;
+            st->fp64_tiles = (int32_t)n64s;
+            const uint32_t it = st->iter + 1u;
+            st->iter = it;
+            if (p.res) {
+                p.res->status = status;
+                p.res->counter = c;
+                if (mark) {
+                    __threadfence_system();
+                    p.res->seq = it;
+                    __threadfence_system();     // push the mark out now, not at kernel end
+                }
+            }
         }
     }
 }
@@ -1042,7 +1082,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
 {
     __shared__ double sf[kMaxTiles];
     __shared__ double slots[kUpdWaves];
-    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, sf, slots);
+    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.mark != 0, sf, slots);
 }
 
 template <int MODEL, int S>
@@ -1110,7 +1150,8 @@ __global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __r
     __shared__ double sf[kMaxTiles];
     __shared__ double slots[kUpdWaves];
     const RowUnit ru = units[blockIdx.x];
-    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, sf, slots);
+    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, false, sf,
+                slots);
 }
 
 __global__ __launch_bounds__(kExpBlock) void k_explore(DevParams p, StepArgs a)

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -33,6 +35,22 @@ bool finite_all(const float* v, size_t n)
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Spin until the completion mark of iteration `want` appears in the pinned
+// result block; false after about 50 ms.
+bool wait_completion(const HostResult* r, uint64_t want)
+{
+    const volatile uint64_t* seq = &r->seq;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t i = 1;; ++i) {
+        if (*seq == want) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return true;
+        }
+        if ((i & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) return false;
+        __builtin_ia32_pause();
+    }
+}
 
 // Savitzky-Golay weights for every step of a horizon of T: row t holds the
 // 2m+1 weights a_j with which the smoothed value at t is sum_j a_j y[s + j],
@@ -445,7 +463,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
         delete h;
         return st;
     }
-    e = hipHostMalloc(reinterpret_cast<void**>(&h->h_res), sizeof(HostResult), hipHostMallocMapped);
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->h_res), sizeof(HostResult), hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p.res), h->h_res, 0);
     if (e != hipSuccess) {
         set_global_error(std::string("pinned result buffer: ") + hipGetErrorString(e));
@@ -604,10 +622,11 @@ extern "C" int mppi_set_controls(mppi_t* h, const float* U, int32_t mem)
     return MPPI_OK;
 }
 
-int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_dev)
+int mppi_ctrl::launch_step(const float* x0_host, const float* x0_dev, float* u0_dev, bool mark)
 {
     StepArgs a;
     std::memset(&a, 0, sizeof a);
+    a.mark = mark ? 1u : 0u;
     if (x0_host) std::memcpy(a.x0, x0_host, sizeof(float) * p.n);
     a.x0_ptr = x0_dev;
     a.u0_dev = u0_dev;
@@ -672,9 +691,12 @@ extern "C" int mppi_step(mppi_t* h, const float* x0, float* u0)
     CHECK_HANDLE(h);
     if (!x0 || !u0) return h->fail(MPPI_E_INVALID, "x0/u0 is NULL");
     if (!finite_all(x0, h->p.n)) return h->fail(MPPI_E_INVALID, "non-finite x0");
-    int s = h->launch_step(x0, nullptr, nullptr);
+    int s = h->launch_step(x0, nullptr, nullptr, true);
     if (s) return s;
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    // the update kernel marks completion in pinned memory after u0 and the
+    // status; spin on it (a stream synchronisation wakes up later), and fall
+    // back to the synchronisation -- which also reports errors -- after 50 ms
+    if (!wait_completion(h->h_res, h->iter)) HIP_TRY(h, hipStreamSynchronize(h->stream));
     const HostResult* r = h->h_res;
     u0[0] = r->u0[0];
     u0[1] = r->u0[1];

@@ -44,7 +44,7 @@ struct mppi_ctrl {
     int configure_tiles(int S);
     int alloc_tile_buffers();
     int retile();
-    int launch_step(const float* x0_host, const float* x0_dev, float* u0_dev);
+    int launch_step(const float* x0_host, const float* x0_dev, float* u0_dev, bool mark = false);
 };
 
 namespace dbas {

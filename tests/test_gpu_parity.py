@@ -359,3 +359,19 @@ def test_noise_export_changes_nothing_else():
         b.noise()
     a.close()
     b.close()
+
+
+def test_synchronous_step_returns_the_iterations_own_u0():
+    """mppi_step returns as soon as the update marks completion in pinned
+    memory: its u0 must be the iteration's U*[0] and its status final, step
+    after step (with adaptive exploration queued behind the update too)."""
+    wl = W.car(K=2048, T=30, J=60)
+    for over in ({}, {"adaptive_explore": True}):
+        c, _ = _ctrl(wl, **over)
+        x = wl["x0"].copy()
+        for i in range(25):
+            u0 = c.step(x)
+            np.testing.assert_array_equal(u0, c.last_optimal()[0])
+            assert c.info()["status"] == 0 and c.get_state()["counter"] == i + 1
+            x = x + np.float32(0.01)
+        c.close()
