@@ -146,8 +146,9 @@ struct mppi_batch {
     uint32_t* d_queue = nullptr;
     BatchIn* d_in = nullptr;
     BatchIn* h_in = nullptr;        // pinned staging of the per-step states and buffer parities
-    int nunits = 0, nrows = 0, nexp = 0, grid = 0;
-    size_t lds = 0, lds_exp = 0;
+    int nunits = 0, nrows = 0, nexp = 0;
+    UnitGroups groups{};
+    size_t lds_exp = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string err;
@@ -183,32 +184,28 @@ struct mppi_batch {
         const int n = (int)ctrls.size();
         params.resize(n);
         versions.resize(n);
-        std::vector<std::pair<double, BatchUnit>> work;
+        std::vector<BatchWork> work;
         std::vector<RowUnit> rows;
         std::vector<int32_t> exp_ids;
-        size_t lds_max = 0;
         lds_exp = 0;
         for (int c = 0; c < n; ++c) {
             params[c] = ctrls[c]->p;
             versions[c] = ctrls[c]->version;
             const DevParams& p = params[c];
-            lds_max = std::max(lds_max, tile_lds_bytes(p.J, p.T, p.n, p.spt));
-            // longest-processing-time order: per-tile work ~ samples x steps x (pairs + fixed)
-            const double cost = (double)std::min(p.spt, p.K) * p.T * ((double)p.P * p.J + 64.0);
-            for (int t = 0; t < p.tiles; ++t) work.push_back({cost, BatchUnit{c, t}});
+            const double cost = tile_cost(p.spt, p.K, p.T, p.P, p.J);
+            const size_t lds = tile_lds_bytes(p.J, p.T, p.n, p.spt);
+            for (int t = 0; t < p.tiles; ++t) work.push_back({cost, p.model, lds, BatchUnit{c, t}});
             for (int r = 0; r < 2 * p.T; r += kUpdBlock / kWave) rows.push_back(RowUnit{c, r});
             if (p.adaptive) {
                 exp_ids.push_back(c);
                 lds_exp = std::max(lds_exp, explore_lds_bytes(p.J, p.T));
             }
         }
-        std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         std::vector<BatchUnit> units(work.size());
-        for (size_t i = 0; i < work.size(); ++i) units[i] = work[i].second;
+        groups = group_units(work, units.data());
         nunits = (int)units.size();
         nrows = (int)rows.size();
         nexp = (int)exp_ids.size();
-        lds = lds_max;
 
         int st;
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
@@ -229,13 +226,12 @@ struct mppi_batch {
 
         int cus = 0;
         if ((st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device), "CU count"))) return st;
-        grid = std::max(1, std::min(nunits, cus * batch_rollout_blocks_per_cu(lds)));
 
         // capture: per-step inputs H2D, persistent rollout, row update, and the
         // exploration rate of the controllers that adapt it
         if ((st = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture"))) return st;
         hipError_t e = hipMemcpyAsync(d_in, h_in, sizeof(BatchIn) * n, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = launch_batch_rollout(d_params, d_units, nunits, d_in, d_queue, grid, lds, stream);
+        if (e == hipSuccess) e = launch_batch_rollouts(d_params, d_units, groups, d_in, d_queue, cus, stream);
         if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, d_in, nullptr, stream);
         if (e == hipSuccess && nexp) e = launch_batch_explore(d_params, d_exp, nexp, d_in, lds_exp, stream);
         hipGraph_t g = nullptr;
@@ -277,8 +273,8 @@ extern "C" int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_dev
     }
     for (mppi_ctrl* c : b->ctrls)
         if (!st) st = c->sync();
-    if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2), "hipMalloc queue");
-    if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2), "queue init");
+    if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2 * kModels), "hipMalloc queue");
+    if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2 * kModels), "queue init");
     if (!st) st = b->hip(hipMalloc(&b->d_in, sizeof(BatchIn) * n), "hipMalloc inputs");
     if (!st) st = b->hip(hipHostMalloc(reinterpret_cast<void**>(&b->h_in), sizeof(BatchIn) * n, 0), "hipHostMalloc inputs");
     if (!st) {

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dbas_mppi.h"
 
 namespace dbas {
@@ -109,6 +111,41 @@ struct BatchUnit {
     int32_t tile;
 };
 
+constexpr int kModels = 3;          // MPPI_QUAD6, MPPI_QUAD5, MPPI_CAR
+
+// The rollout units of a batched launch, grouped by model: one persistent
+// kernel per model present (a kernel that holds every model's tile needs more
+// registers and runs each of them slower).  Group m is units
+// [begin[m], begin[m] + count[m]) of the list, longest first; lds[m] is the
+// dynamic LDS its kernel needs and work[m] the sum of its units' estimates.
+// The queue of group m is words 2m and 2m + 1.
+struct UnitGroups {
+    int begin[kModels];
+    int count[kModels];
+    size_t lds[kModels];
+    double work[kModels];
+};
+
+// A rollout unit before grouping, with its model, its estimated work and the
+// dynamic LDS of its tile.
+struct BatchWork {
+    double cost;
+    int32_t model;
+    size_t lds;
+    BatchUnit unit;
+};
+
+// Per-tile work estimate for longest-first ordering: samples x steps x
+// (pairs + a fixed part).
+inline double tile_cost(int S, int K, int T, int P, int J)
+{
+    return (double)(S < K ? S : K) * T * ((double)P * J + 64.0);
+}
+
+// Sort `work` by model, then longest first (stable), write the units to `out`
+// and return the groups.
+UnitGroups group_units(std::vector<BatchWork>& work, BatchUnit* out);
+
 inline int state_dim(int model) { return model == MPPI_QUAD6 ? 6 : model == MPPI_QUAD5 ? 5 : 4; }
 
 // LDS obstacle slots (at least one, so the carve-up never has a zero-size array).
@@ -178,8 +215,10 @@ inline size_t tile_lds_bytes(int J, int T, int n, int S)
 // Kernel launchers (mppi_kernels.hip).
 hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s);
-hipError_t launch_batch_rollout(const DevParams* d_params, const BatchUnit* d_units, int nunits,
-                                const BatchIn* d_in, uint32_t* d_queue, int grid, size_t lds, hipStream_t s);
+// One persistent rollout launch per group, in order of decreasing work, each
+// over min(units, cus x resident blocks) workgroups.
+hipError_t launch_batch_rollouts(const DevParams* d_params, const BatchUnit* d_units, const UnitGroups& g,
+                                 const BatchIn* d_in, uint32_t* d_queue, int cus, hipStream_t s);
 hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, const BatchIn* d_in,
                                float* d_u0s, hipStream_t s);
 hipError_t launch_explore(const DevParams& p, const StepArgs& a, hipStream_t s);
@@ -187,7 +226,7 @@ hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids,
                                 size_t lds, hipStream_t s);
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s);
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s);
-int batch_rollout_blocks_per_cu(size_t lds);
+int batch_rollout_blocks_per_cu(int model, size_t lds);
 bool tile_samples_supported(int S);
 
 }  // namespace dbas

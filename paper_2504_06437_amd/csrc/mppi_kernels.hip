@@ -38,6 +38,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace dbas {
 namespace {
 
@@ -1105,9 +1107,11 @@ __device__ __forceinline__ void dispatch_s(const DevParams& p, int tile, const X
     }
 }
 
-// Persistent rollout over a work list of (controller, tile) units, taken in
-// list order (the host sorts it longest-first).  Every block leaves the loop
-// once the list is exhausted; the last block to leave resets the queue.
+// Persistent rollout over a work list of (controller, tile) units of one
+// model, taken in list order (the host sorts it longest-first).  Every block
+// leaves the loop once the list is exhausted; the last block to leave resets
+// the queue.
+template <int MODEL>
 __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* __restrict__ ps,
                                                               const BatchUnit* __restrict__ units, int nunits,
                                                               const BatchIn* __restrict__ in, uint32_t* queue)
@@ -1126,11 +1130,7 @@ __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* _
 #pragma unroll
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
         xs.parity = in[bu.ctrl].parity;
-        switch (p.model) {
-        case MPPI_QUAD6: dispatch_s<MPPI_QUAD6>(p, bu.tile, xs, smem); break;
-        case MPPI_QUAD5: dispatch_s<MPPI_QUAD5>(p, bu.tile, xs, smem); break;
-        default: dispatch_s<MPPI_CAR>(p, bu.tile, xs, smem); break;
-        }
+        dispatch_s<MODEL>(p, bu.tile, xs, smem);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -1241,12 +1241,56 @@ hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_rollout(const DevParams* d_params, const BatchUnit* d_units, int nunits,
-                                const BatchIn* d_in, uint32_t* d_queue, int grid, size_t lds, hipStream_t s)
+namespace {
+
+using BatchRolloutKernel = void (*)(const DevParams*, const BatchUnit*, int, const BatchIn*, uint32_t*);
+
+BatchRolloutKernel batch_rollout_kernel(int model)
 {
-    hipLaunchKernelGGL(k_batch_rollout, dim3(grid), dim3(kRollBlock), lds, s, d_params, d_units, nunits, d_in,
-                       d_queue);
-    return hipGetLastError();
+    switch (model) {
+    case MPPI_QUAD6: return k_batch_rollout<MPPI_QUAD6>;
+    case MPPI_QUAD5: return k_batch_rollout<MPPI_QUAD5>;
+    default: return k_batch_rollout<MPPI_CAR>;
+    }
+}
+
+}  // namespace
+
+UnitGroups group_units(std::vector<BatchWork>& work, BatchUnit* out)
+{
+    std::stable_sort(work.begin(), work.end(), [](const BatchWork& a, const BatchWork& b) {
+        return a.model != b.model ? a.model < b.model : a.cost > b.cost;
+    });
+    UnitGroups g{};
+    for (int m = 0; m < kModels; ++m) g.begin[m] = -1;
+    for (size_t i = 0; i < work.size(); ++i) {
+        const int m = work[i].model;
+        if (g.begin[m] < 0) g.begin[m] = (int)i;
+        ++g.count[m];
+        g.work[m] += work[i].cost;
+        if (work[i].lds > g.lds[m]) g.lds[m] = work[i].lds;
+        out[i] = work[i].unit;
+    }
+    for (int m = 0; m < kModels; ++m)
+        if (g.begin[m] < 0) g.begin[m] = 0;
+    return g;
+}
+
+hipError_t launch_batch_rollouts(const DevParams* d_params, const BatchUnit* d_units, const UnitGroups& g,
+                                 const BatchIn* d_in, uint32_t* d_queue, int cus, hipStream_t s)
+{
+    int order[kModels] = {0, 1, 2};
+    std::stable_sort(order, order + kModels, [&](int a, int b) { return g.work[a] > g.work[b]; });
+    for (int i = 0; i < kModels; ++i) {
+        const int m = order[i];
+        if (g.count[m] == 0) continue;
+        const int grid = std::max(1, std::min(g.count[m], cus * batch_rollout_blocks_per_cu(m, g.lds[m])));
+        hipLaunchKernelGGL(batch_rollout_kernel(m), dim3(grid), dim3(kRollBlock), g.lds[m], s, d_params,
+                           d_units + g.begin[m], g.count[m], d_in, d_queue + 2 * m);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_batch_update(const DevParams* d_params, const RowUnit* d_units, int nunits, const BatchIn* d_in,
@@ -1282,10 +1326,12 @@ hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d
     return hipGetLastError();
 }
 
-int batch_rollout_blocks_per_cu(size_t lds)
+int batch_rollout_blocks_per_cu(int model, size_t lds)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_rollout, kRollBlock, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_rollout_kernel(model), kRollBlock, lds) !=
+        hipSuccess)
+        return 1;
     return blocks > 0 ? blocks : 1;
 }
 

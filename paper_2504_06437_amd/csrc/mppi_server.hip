@@ -138,14 +138,14 @@ struct mppi_server {
 
     // Lays out the launch of `picks` in the slot's pinned staging; returns the
     // bytes to copy.  Called with the lock held.
-    size_t stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows_out, size_t* off_in, size_t* off_rows,
-                 size_t* off_units, int* nexp_out, size_t* off_exp, size_t* lds_exp_out);
+    size_t stage(Slot& sl, UnitGroups* groups, int* nrows_out, size_t* off_in, size_t* off_rows, size_t* off_units,
+                 int* nexp_out, size_t* off_exp, size_t* lds_exp_out);
     void scheduler();
     void waiter(int si);
 };
 
-size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows_out, size_t* off_in,
-                          size_t* off_rows, size_t* off_units, int* nexp_out, size_t* off_exp, size_t* lds_exp_out)
+size_t mppi_server::stage(Slot& sl, UnitGroups* groups, int* nrows_out, size_t* off_in, size_t* off_rows,
+                          size_t* off_units, int* nexp_out, size_t* off_exp, size_t* lds_exp_out)
 {
     const auto& picks = sl.picks;
     const int n = (int)picks.size();
@@ -197,8 +197,7 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
     int nexp = 0;
     size_t lds_exp = 0;
     size_t ref_at = 0;
-    size_t lds = 0;
-    std::vector<std::pair<double, BatchUnit>> work;
+    std::vector<BatchWork> work;
     work.reserve(nunits);
     int r_at = 0;
     for (int i = 0; i < n; ++i) {
@@ -229,9 +228,9 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
         ++h->iter;
 
         for (int r = 0; r < 2 * q.T; r += kUpdBlock / kWave) rows[r_at++] = RowUnit{i, r};
-        const double cost = (double)std::min(q.spt, q.K) * q.T * ((double)q.P * q.J + 64.0);
-        for (int t = 0; t < q.tiles; ++t) work.push_back({cost, BatchUnit{i, t}});
-        lds = std::max(lds, tile_lds_bytes(q.J, q.T, q.n, q.spt));
+        const double cost = tile_cost(q.spt, q.K, q.T, q.P, q.J);
+        const size_t lds = tile_lds_bytes(q.J, q.T, q.n, q.spt);
+        for (int t = 0; t < q.tiles; ++t) work.push_back({cost, q.model, lds, BatchUnit{i, t}});
         if (q.adaptive) {
             exp_ids[nexp++] = i;
             lds_exp = std::max(lds_exp, explore_lds_bytes(q.J, q.T));
@@ -239,10 +238,7 @@ size_t mppi_server::stage(Slot& sl, size_t* lds_out, int* nunits_out, int* nrows
     }
     *nexp_out = nexp;
     *lds_exp_out = lds_exp;
-    std::stable_sort(work.begin(), work.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    for (int u = 0; u < nunits; ++u) units[u] = work[u].second;
-    *lds_out = lds;
-    *nunits_out = nunits;
+    *groups = group_units(work, units);
     *nrows_out = nrows;
     return total;
 }
@@ -265,10 +261,10 @@ void mppi_server::scheduler()
         seen = ~0ull;                       // look again at once: more may fit in another slot
         sl.busy = true;
         in_flight += (int)sl.picks.size();
-        size_t lds = 0, off_in = 0, off_rows = 0, off_units = 0, off_exp = 0, lds_exp = 0;
-        int nunits = 0, nrows = 0, nexp = 0;
-        const size_t bytes =
-            stage(sl, &lds, &nunits, &nrows, &off_in, &off_rows, &off_units, &nexp, &off_exp, &lds_exp);
+        size_t off_in = 0, off_rows = 0, off_units = 0, off_exp = 0, lds_exp = 0;
+        int nrows = 0, nexp = 0;
+        UnitGroups groups{};
+        const size_t bytes = stage(sl, &groups, &nrows, &off_in, &off_rows, &off_units, &nexp, &off_exp, &lds_exp);
         ++stats.launches;
         batched_requests += (int64_t)sl.picks.size();
         lk.unlock();
@@ -278,10 +274,7 @@ void mppi_server::scheduler()
         const auto* d_in = reinterpret_cast<const BatchIn*>(sl.d_stage + off_in);
         const auto* d_rows = reinterpret_cast<const RowUnit*>(sl.d_stage + off_rows);
         const auto* d_units = reinterpret_cast<const BatchUnit*>(sl.d_stage + off_units);
-        if (e == hipSuccess) {
-            const int grid = std::max(1, std::min(nunits, cus * batch_rollout_blocks_per_cu(lds)));
-            e = launch_batch_rollout(d_params, d_units, nunits, d_in, sl.d_queue, grid, lds, sl.stream);
-        }
+        if (e == hipSuccess) e = launch_batch_rollouts(d_params, d_units, groups, d_in, sl.d_queue, cus, sl.stream);
         if (e == hipSuccess) e = launch_batch_update(d_params, d_rows, nrows, d_in, nullptr, sl.stream);
         if (e == hipSuccess && nexp)
             e = launch_batch_explore(d_params, reinterpret_cast<const int32_t*>(sl.d_stage + off_exp), nexp, d_in,
@@ -387,8 +380,8 @@ extern "C" int mppi_server_create(const mppi_server_config* cfg, mppi_server_t**
     for (Slot& sl : s->slots) {
         if (e == hipSuccess) e = hipStreamCreate(&sl.stream);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_queue), sizeof(uint32_t) * 2);
-        if (e == hipSuccess) e = hipMemset(sl.d_queue, 0, sizeof(uint32_t) * 2);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_queue), sizeof(uint32_t) * 2 * kModels);
+        if (e == hipSuccess) e = hipMemset(sl.d_queue, 0, sizeof(uint32_t) * 2 * kModels);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {

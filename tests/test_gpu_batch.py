@@ -80,3 +80,34 @@ def test_batch_replays_follow_obstacle_changes():
     batch.close()
     for c in alone + mixed:
         c.close()
+
+
+@pytest.mark.parametrize("models", [("quad6", "quad5", "car"), ("quad5",), ("car", "car")])
+def test_batch_groups_by_model(models):
+    """The batched rollout runs one persistent launch per model present, each
+    with its own queue; every controller still equals its standalone run, on
+    replays too (each launch's queue is reset by its last workgroup), and a
+    shape point count other than the model's default takes the runtime-P tile."""
+    from paper_2504_06437_amd.controller import Batch
+    rng = np.random.Generator(np.random.PCG64(33))
+    wls = []
+    for i, m in enumerate(models):
+        wl = W.mixed_controller(rng, 300 + i, K=int(rng.integers(100, 900)), T=int(rng.integers(6, 25)),
+                                J=int(rng.integers(1, 50)), model=m)
+        wl["U0"] = W.random_controls(rng, wl["params"]["T"], 0.2)
+        wls.append(wl)
+    if models == ("car", "car"):
+        shape = np.float32([[-1.0, 0.0], [0.0, 0.0], [1.0, 0.0]])
+        wls[1]["params"]["shape"] = shape.tolist()
+    alone = [_make(wl) for wl in wls]
+    mixed = [_make(wl) for wl in wls]
+    batch = Batch(mixed)
+    for _ in range(3):
+        u_b, sts = batch.step([wl["x0"] for wl in wls])
+        assert np.all(sts == 0)
+        for i, (a, m, wl) in enumerate(zip(alone, mixed, wls)):
+            np.testing.assert_array_equal(a.step(wl["x0"]), u_b[i])
+            np.testing.assert_array_equal(a.costs(), m.costs())
+    batch.close()
+    for c in alone + mixed:
+        c.close()
