@@ -164,7 +164,7 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
-    b += 32;                                    // work counters, cshift, beta_d
+    b += 64;                                    // pool waves per SIMD, owner SIMD, cshift
     return b;
 }
 

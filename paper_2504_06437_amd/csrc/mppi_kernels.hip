@@ -339,8 +339,8 @@ struct TileLds {
     float* ref;       // [(T+1) n], local frame
     double* e;        // [kMaxTile] tile exponentials
     double* slots;    // [16] block-reduction slots
-    int* work;        // [2] work counters of the barrier stages, then
-                      // cshift (double, at byte 8)
+    int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
+                      // cshift (double, at byte 32)
     // chunk slots, two buffers each (buffer b at offset b * cs):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, 0)
     float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
@@ -365,7 +365,7 @@ __device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int 
     L.slots = reinterpret_cast<double*>(smem + off);
     off += 16 * 8;
     L.work = reinterpret_cast<int*>(smem + off);
-    off += 32;
+    off += 64;
     L.cs = cs;
     L.in = reinterpret_cast<float4*>(smem + off);
     off += (size_t)2 * cs * 16;
@@ -384,6 +384,8 @@ struct X0 {
 
 constexpr int kRollWaves = kRollBlock / kWave;
 constexpr int kSimdsPerCU = 4;
+// s_getreg operand for the SIMD of the issuing wave: HW_ID bits [5:4].
+constexpr int kHwIdSimd = (1 << 11) | (4 << 6) | 4;
 constexpr int kUpdWaves = kUpdBlock / kWave;
 
 // Sum of a float pair over the block (NW waves); every thread gets it.
@@ -409,7 +411,10 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 }
 
 // This thread's share, over threads [first, block), of the fused barrier at
-// two (local-frame) poses a and b.
+// two (local-frame) poses a and b: every shape point against obstacles
+// i0, i0 + stride, ... (PM = compile-time bound on P), and with a costmap
+// the costmap term of shape point i0.
+template <int PM>
 __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int P, int first, float ax, float ay,
                                        float ath, float bx, float by, float bth, float inv_res, float offx,
                                        float offy)
@@ -420,17 +425,21 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
     float acc_a = 0.0f, acc_b = 0.0f;
     const int J = p.J;
     const int i0 = (int)threadIdx.x - first;
-    for (int idx = i0; idx < P * J; idx += kRollBlock - first) {
-        const int i = idx / J, j = idx - i * J;
-        const float u = p.shape[i][0], w = p.shape[i][1];
+    for (int j = i0; j < J; j += kRollBlock - first) {
         const float4 o = L.obs[j];
-        const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
-        const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
-        const float dax = pax - o.x, day = pay - o.y, dbx = pbx - o.x, dby = pby - o.y;
-        acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.z)), p.h_eps);
-        acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.z)), p.h_eps);
+#pragma unroll
+        for (int i = 0; i < PM; ++i) {
+            if (i < P) {
+                const float u = p.shape[i][0], w = p.shape[i][1];
+                const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
+                const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
+                const float dax = pax - o.x, day = pay - o.y, dbx = pbx - o.x, dby = pby - o.y;
+                acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.z)), p.h_eps);
+                acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.z)), p.h_eps);
+            }
+        }
     }
-    if (p.sdf != nullptr && i0 < P) {
+    if (p.sdf != nullptr && i0 >= 0 && i0 < P) {
         const float u = p.shape[i0][0], w = p.shape[i0][1];
         const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
         const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
@@ -513,7 +522,7 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 // shuffles.
 // Inputs, poses and barrier values are double-buffered by chunk parity.
 // ---------------------------------------------------------------------------
-template <int MODEL, int S, int PT>
+template <int MODEL, int S, int PT, bool SC>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int NS = Model<MODEL>::NS;
@@ -545,6 +554,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
         L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(-(r * r)), 0.0f);
     }
+    if (tid < 8) L.work[tid] = 0;
     for (int t = tid; t < T; t += kRollBlock) L.U[t] = make_float2(Uin[2 * t], Uin[2 * t + 1]);
     for (int i = tid; i < (T + 1) * NS; i += kRollBlock) {
         const int a = i % NS;
@@ -560,9 +570,24 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     }
     lds_barrier();
 
+    // With SC the barrier units of a stage are shared out by SIMD (see
+    // barrier_chunk): each wave learns its SIMD and, outside the owner waves,
+    // its slot among the pool waves of that SIMD.
+    [[maybe_unused]] const int simd = SC ? __builtin_amdgcn_s_getreg(kHwIdSimd) : 0;
+    int pslot = 0;
+    if constexpr (SC) {
+        if (lane == 0) {
+            if (wave >= DW) pslot = atomicAdd(&L.work[simd], 1);
+            else if (wave == 0) L.work[4] = simd;
+        }
+        pslot = __builtin_amdgcn_readfirstlane(pslot);
+    }
+    [[maybe_unused]] int my_pool = 1;                   // pool waves on this wave's SIMD
+    [[maybe_unused]] int serve[kSimdsPerCU] = {0, 1, 2, 3};   // the SIMD that serves each unit class
+
     // beta_0 = fused B(h(x0)); beta_d = fused B(h(x_d)), x_d = x_ref[T].
     const float2 b0d = block_sum_f2<kRollWaves>(
-        fused_barrier_share2(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
+        fused_barrier_share2<PM>(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
                              inv_res, offx, offy),
         L.slots);
     const float beta0 = b0d.x, beta_d = b0d.y;
@@ -673,9 +698,19 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    // fused barrier of every (step, sample) of chunk c, in units of one wave
-    // taken from the work counter
-    auto barrier_chunk = [&](int c, int* counter) __attribute__((always_inline)) {
+    // Fused barrier of every (step, sample) of chunk c, in units of one wave.
+    // With SC the units are shared out by SIMD, not taken first come first
+    // served: a SIMD's older waves win the issue arbitration, so under a
+    // shared counter they took the most units and the SIMD of the owner wave
+    // finished last.  Unit u belongs to class u mod 4; class cl is served by
+    // the SIMD of rank 3 - cl from the owner wave's SIMD (the class that is
+    // one unit short, when there is one, goes to the owner's SIMD), or,
+    // should that SIMD have no pool wave, by the next one that has.  Within a
+    // SIMD the pool waves take the class's units round-robin by slot; the
+    // owner waves take none.  Without SC (the batched kernel, where the
+    // extra state costs registers) every wave takes units from an LDS
+    // counter.  Which wave computes a unit never changes its arithmetic.
+    auto barrier_chunk = [&](int c) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
         // split: among the splits that give every wave of the noise pool a
         // unit, the one whose units, spread over the CU's SIMDs, cost least:
@@ -709,11 +744,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         const int units = ((items << lg) + kWave - 1) / kWave;
         const float4* pz = L.pose + (c & 1) * L.cs;
         float* bv = L.bval + (c & 1) * L.cs;
-        for (;;) {
-            int u = 0;
-            if (lane == 0) u = atomicAdd(counter, 1);
-            u = __shfl(u, 0);
-            if (u >= units) break;
+        auto unit = [&](int u) __attribute__((always_inline)) {
             const int g = u * kWave + lane;
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = 0.0f;
@@ -722,13 +753,43 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
                                               offy);
             for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             if (sp == 0 && item < items) bv[item] = part;
+        };
+        if constexpr (SC) {
+            if (wave < DW) return;
+#pragma unroll
+            for (int cl = 0; cl < kSimdsPerCU; ++cl) {
+                if (serve[cl] != simd) continue;
+                for (int u = cl + kSimdsPerCU * pslot; u < units; u += kSimdsPerCU * my_pool) unit(u);
+            }
+        } else {
+            int* counter = &L.work[5 + ((c + 1) & 1)];
+            for (;;) {
+                int u = 0;
+                if (lane == 0) u = atomicAdd(counter, 1);
+                u = __shfl(u, 0);
+                if (u >= units) break;
+                unit(u);
+            }
         }
     };
 
     inputs_chunk(0, 0);
     lds_barrier();
+    // (the SIMD counts are final: the block reductions since have synchronised)
+    if constexpr (SC) {
+        my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
+        const int osimd = __builtin_amdgcn_readfirstlane(L.work[4]);
+#pragma unroll
+        for (int cl = 0; cl < kSimdsPerCU; ++cl) {
+            int sv = (osimd + kSimdsPerCU - 1 - cl) & (kSimdsPerCU - 1);
+            for (int t = 0; t < kSimdsPerCU && L.work[sv] == 0; ++t) sv = (sv + 1) & (kSimdsPerCU - 1);
+            serve[cl] = __builtin_amdgcn_readfirstlane(sv);
+        }
+    }
     for (int st_k = 0; st_k <= nch + 1; ++st_k) {
-        if (tid == 0) L.work[(st_k + 1) & 1] = 0;      // counter of the next stage
+        if constexpr (!SC) {
+            if (tid == 0) L.work[5 + ((st_k + 1) & 1)] = 0;      // counter of the next stage
+        }
         if (wave < DW) {
             if (owner && st_k >= 2) beta_chunk(st_k - 2);
             if (owner && st_k < nch) dynamics_chunk(st_k);
@@ -737,15 +798,15 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             if (st_k == 1 && tid == POOL0) {
                 const double g = (double)p.gamma_b;
                 const double geo = g * (1.0 - pow(g, (double)T)) / (1.0 - g);
-                *reinterpret_cast<double*>(L.work + 2) =
+                *reinterpret_cast<double*>(L.work + 8) =
                     (double)p.r_b * (-(double)beta_d * g / (1.0 - g) * ((double)T - geo));
             }
         }
-        if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1, &L.work[st_k & 1]);
+        if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1);
         lds_barrier();
     }
     // (the stage loop always runs stage 1, which wrote it)
-    const double cshift = *reinterpret_cast<const double*>(L.work + 2);
+    const double cshift = *reinterpret_cast<const double*>(L.work + 8);
     if (owner) {
         const float* rf = L.ref + T * NS;
         float phi = 0.0f;
@@ -762,19 +823,58 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // otherwise wait for them)
     const double Sd = ((double)S_hi + (double)S_lo) + cshift;
     const bool ok = valid && isfinite(Sd);
-    const double rho_b = block_min_d<kRollWaves>(ok ? Sd : INFINITY, L.slots);
-    const bool any = isfinite(rho_b);
-    const bool use64 = any && (p.normaliser == MPPI_NORM_ON ||
-                               (p.normaliser == MPPI_NORM_AUTO && fabs(rho_b) >= 1024.0 * (double)p.lambda));
-    double ek = 0.0;
-    if (ok) {
-        const double d = (Sd - rho_b) / (double)p.lambda;
-        ek = use64 ? exp(-d) : (double)expf(-(float)d);
+    auto wants64 = [&](double rho) {
+        return isfinite(rho) && (p.normaliser == MPPI_NORM_ON ||
+                                 (p.normaliser == MPPI_NORM_AUTO && fabs(rho) >= 1024.0 * (double)p.lambda));
+    };
+    auto weight = [&](double rho, bool u64) {
+        double ek = 0.0;
+        if (ok) {
+            const double d = (Sd - rho) / (double)p.lambda;
+            ek = u64 ? exp(-d) : (double)expf(-(float)d);
+        }
+        return ek;
+    };
+    double rho_b, eta_b, ek = 0.0;
+    if constexpr (DW == 1) {
+        // every sample is on wave 0: reduce over its first S lanes and
+        // publish through LDS behind one barrier
+        if (wave == 0) {
+            double m = ok ? Sd : INFINITY;
+#pragma unroll
+            for (int o = S / 2; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o));
+            m = __shfl(m, 0);
+            const bool u64 = wants64(m);
+            ek = weight(m, u64);
+            if (owner) L.e[tid] = ek;
+            double es;
+            if (u64) {
+                es = ek;
+#pragma unroll
+                for (int o = S / 2; o >= 1; o >>= 1) es += __shfl_xor(es, o);
+            } else {
+                float ef = (float)ek;
+#pragma unroll
+                for (int o = S / 2; o >= 1; o >>= 1) ef += __shfl_xor(ef, o);
+                es = (double)ef;
+            }
+            if (tid == 0) {
+                L.slots[0] = m;
+                L.slots[1] = es;
+            }
+        }
+        lds_barrier();
+        rho_b = L.slots[0];
+        eta_b = L.slots[1];
+    } else {
+        rho_b = block_min_d<kRollWaves>(ok ? Sd : INFINITY, L.slots);
+        ek = weight(rho_b, wants64(rho_b));
+        if (owner) L.e[tid] = ek;
+        if (wants64(rho_b)) eta_b = block_sum_d<kRollWaves>(ek, L.slots);
+        else eta_b = (double)block_sum_f<kRollWaves>((float)ek, L.slots);
     }
-    if (owner) L.e[tid] = ek;
-    double eta_b;
-    if (use64) eta_b = block_sum_d<kRollWaves>(ek, L.slots);
-    else eta_b = (double)block_sum_f<kRollWaves>((float)ek, L.slots);
+    const bool any = isfinite(rho_b);
+    const bool use64 = wants64(rho_b);
 
     // N_b[2t + c] = sum over the tile's samples of e_k du[t][c][k].  The
     // noise is never stored in device memory on the way: it is kept in LDS
@@ -783,8 +883,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // exports it).  TPT consecutive threads share a step t, each
     // summing every TPT-th sample in order, then combining across the TPT
     // threads.
+    // (at least eight samples per thread: fewer shuffle rounds)
     int tpt = 1;
-    while (tpt < 64 && (tpt << 1) * T <= kRollBlock) tpt <<= 1;
+    while (tpt < 64 && (tpt << 1) * T <= kRollBlock && (tpt << 1) * 8 <= S) tpt <<= 1;
     const int steps_per_pass = kRollBlock / tpt;
     const int part = tid & (tpt - 1);
     const int k0 = tile * S;
@@ -1077,7 +1178,7 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 #pragma unroll
     for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0_ptr ? (i < p.n ? a.x0_ptr[i] : 0.0f) : a.x0[i];
     xs.parity = a.parity;
-    rollout_tile<MODEL, S, PT>(p, blockIdx.x, xs, smem);
+    rollout_tile<MODEL, S, PT, true>(p, blockIdx.x, xs, smem);
 }
 
 __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
@@ -1091,8 +1192,8 @@ template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD) rollout_tile<MODEL, S, PD>(p, tile, xs, smem);
-    else rollout_tile<MODEL, S, 0>(p, tile, xs, smem);
+    if (p.P == PD) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
+    else rollout_tile<MODEL, S, 0, false>(p, tile, xs, smem);
 }
 
 template <int MODEL>
