@@ -19,6 +19,8 @@ bracketed by device synchronisation.  Also reported:
     launch vs the same 64 stepped one after another through the plain path,
   * the served path: 256 robots sending Poisson 50 Hz request streams to the
     continuous-batching server (p50/p99 arrival-to-response latency),
+  * the closed-loop missions (success, path error, average speed) on
+    synthetic layouts with the paper's mission settings,
   * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -388,6 +390,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-missions", action="store_true")
+    ap.add_argument("--mission-runs", type=int, default=10)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
@@ -444,6 +448,11 @@ def main():
     if not args.no_served:
         print(f"[bench] served path: 256 robots x 50 Hz for {args.serve_seconds:g} s", file=sys.stderr, flush=True)
         out["served"] = bench_served(args.serve_seconds)
+    if not args.no_missions:
+        from paper_2504_06437_amd import mission
+        print(f"[bench] missions: {args.mission_runs} closed-loop runs each", file=sys.stderr, flush=True)
+        out["missions"] = {"note": "synthetic layouts with the paper's mission settings; not its layouts",
+                           "results": [mission.run_mission(m, args.mission_runs) for m in (1, 2, 3)]}
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
