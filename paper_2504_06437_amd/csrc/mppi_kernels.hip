@@ -163,6 +163,27 @@ __device__ __forceinline__ double block_sum_d(double v, double* slots)
     return r;
 }
 
+// two sums with one pair of barriers; slots holds at least 2 NW doubles
+template <int NW>
+__device__ __forceinline__ double2 block_sum_d2(double a, double b, double* slots)
+{
+    a = wave_sum_d(a);
+    b = wave_sum_d(b);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        slots[threadIdx.x >> 6] = a;
+        slots[NW + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    double ra = slots[0], rb = slots[NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+        ra += slots[i];
+        rb += slots[NW + i];
+    }
+    return make_double2(ra, rb);
+}
+
 template <int NW>
 __device__ __forceinline__ float block_sum_f(float v, double* slots)
 {
@@ -1000,33 +1021,64 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
     float* Uout = p.U + (size_t)((parity + 1u) & 1u) * T * kM;
     const bool first = row0 == 0;
 
-    double m = INFINITY;
-    for (int b = tid; b < nt; b += kUpdBlock) m = fmin(m, p.rho_b[b]);
+    // Every load that does not depend on the merge is issued first: this
+    // wave's row of partN (its first kPre elements per lane), U_r, and, with
+    // at most one tile per thread, the tile's scalars.
+    constexpr int kPre = 8;
+    const int r = row0 + wave;
+    const bool has_row = r < 2 * T;
+    const double* row = p.partN + (size_t)(has_row ? r : 0) * nt;
+    double pre[kPre];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) pre[i] = (has_row && lane + i * kWave < nt) ? row[lane + i * kWave] : 0.0;
+    const float u_in = has_row ? Uin[r] : 0.0f;
+    const bool one = nt <= kUpdBlock;
+    double rb1 = INFINITY, eb1 = 0.0, fl1 = 0.0;
+    if (one && tid < nt) {
+        rb1 = p.rho_b[tid];
+        eb1 = p.eta_b[tid];
+        fl1 = (double)p.flag_b[tid];
+    }
+
+    double m = rb1;
+    if (!one)
+        for (int b = tid; b < nt; b += kUpdBlock) m = fmin(m, p.rho_b[b]);
     const double rho = block_min_d<kUpdWaves>(m, slots);
     double es = 0.0, n64 = 0.0;
-    for (int b = tid; b < nt; b += kUpdBlock) {
-        const double rb = p.rho_b[b];
-        const double f = (isfinite(rho) && isfinite(rb)) ? exp(-(rb - rho) / (double)p.lambda) : 0.0;
-        sf[b] = f;
-        if (first) p.f_b[b] = f;
-        es += f * p.eta_b[b];
-        n64 += (double)p.flag_b[b];
+    if (one) {
+        if (tid < nt) {
+            const double f = (isfinite(rho) && isfinite(rb1)) ? exp(-(rb1 - rho) / (double)p.lambda) : 0.0;
+            sf[tid] = f;
+            if (first) p.f_b[tid] = f;
+            es = f * eb1;
+            n64 = fl1;
+        }
+    } else {
+        for (int b = tid; b < nt; b += kUpdBlock) {
+            const double rb = p.rho_b[b];
+            const double f = (isfinite(rho) && isfinite(rb)) ? exp(-(rb - rho) / (double)p.lambda) : 0.0;
+            sf[b] = f;
+            if (first) p.f_b[b] = f;
+            es += f * p.eta_b[b];
+            n64 += (double)p.flag_b[b];
+        }
     }
-    const double eta = block_sum_d<kUpdWaves>(es, slots);      // also publishes sf to the block
-    const double n64s = block_sum_d<kUpdWaves>(n64, slots);
+    const double2 sums = block_sum_d2<kUpdWaves>(es, n64, slots);     // also publishes sf to the block
+    const double eta = sums.x, n64s = sums.y;
     const bool ok = isfinite(rho) && isfinite(eta) && eta > 0.0;
 
-    const int r = row0 + wave;
-    if (r < 2 * T) {
+    if (has_row) {
         float us;
         if (ok) {
-            const double* row = p.partN + (size_t)r * nt;
             double a = 0.0;
-            for (int b = lane; b < nt; b += kWave) a += sf[b] * row[b];
+#pragma unroll
+            for (int i = 0; i < kPre; ++i)
+                if (lane + i * kWave < nt) a += sf[lane + i * kWave] * pre[i];
+            for (int b = lane + kPre * kWave; b < nt; b += kWave) a += sf[b] * row[b];
             a = wave_sum_d(a);
-            us = (float)((double)Uin[r] + a / eta);
+            us = (float)((double)u_in + a / eta);
         } else {
-            us = Uin[r];
+            us = u_in;
         }
         if (lane == 0) {
             p.Ustar[r] = us;
@@ -1184,7 +1236,7 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
 {
     __shared__ double sf[kMaxTiles];
-    __shared__ double slots[kUpdWaves];
+    __shared__ double slots[2 * kUpdWaves];
     update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.mark != 0, sf, slots);
 }
 
@@ -1249,7 +1301,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __r
                                                             const BatchIn* __restrict__ in, float* u0s)
 {
     __shared__ double sf[kMaxTiles];
-    __shared__ double slots[kUpdWaves];
+    __shared__ double slots[2 * kUpdWaves];
     const RowUnit ru = units[blockIdx.x];
     update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, false, sf,
                 slots);
