@@ -606,12 +606,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     [[maybe_unused]] int my_pool = 1;                   // pool waves on this wave's SIMD
     [[maybe_unused]] int serve[kSimdsPerCU] = {0, 1, 2, 3};   // the SIMD that serves each unit class
 
-    // beta_0 = fused B(h(x0)); beta_d = fused B(h(x_d)), x_d = x_ref[T].
-    const float2 b0d = block_sum_f2<kRollWaves>(
-        fused_barrier_share2<PM>(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1], L.ref[T * NS + 2],
-                             inv_res, offx, offy),
-        L.slots);
-    const float beta0 = b0d.x, beta_d = b0d.y;
+    float beta0 = 0.0f, beta_d = 0.0f;      // fused B(h(x0)), fused B(h(x_d)), formed below
 
     // ---- setup: lanes 0..S-1 own one sample each ----
     const bool owner = tid < S;
@@ -639,7 +634,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // added in FP64 (cshift), so a large beta_d cannot swamp the FP32 sums;
     // one lane of the noise pool forms it during the second stage and leaves
     // it in LDS.
-    float beta = beta0;
+    float beta = 0.0f;
     float S_hi = 0.0f, S_lo = 0.0f;
 
     float sa2[PM], sb2[PM], ss[PM];       // 2 s_i and |s_i|^2
@@ -794,8 +789,20 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    inputs_chunk(0, 0);
-    lds_barrier();
+    // The first chunk's inputs, on the upper half of the workgroup, while the
+    // threads below J form beta_0 = fused B(h(x0)) and beta_d = fused
+    // B(h(x_d)), x_d = x_ref[T]; the block reduction's barriers then order
+    // both before stage 0.
+    if (tid >= kRollBlock / 2) inputs_chunk(0, kRollBlock / 2);
+    {
+        const float2 b0d = block_sum_f2<kRollWaves>(
+            fused_barrier_share2<PM>(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1],
+                                     L.ref[T * NS + 2], inv_res, offx, offy),
+            L.slots);
+        beta0 = b0d.x;
+        beta_d = b0d.y;
+        beta = beta0;
+    }
     // (the SIMD counts are final: the block reductions since have synchronised)
     if constexpr (SC) {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
