@@ -474,36 +474,70 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 
 // Part of the fused barrier of one pose: every shape point against obstacles
 // j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus, with a costmap,
-// the costmap terms of shape points j0, j0 + js, ... below P.  With e = pose - o and d_i the rotated offset of point i,
-// h_i = |e + d_i|^2 - r^2 = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2: the first term
-// is shared by the P points of an obstacle and |d_i|^2 = |s_i|^2 is fixed,
-// so a pair costs one add and two FMAs.  (sa2, sb2) = 2 s_i, ss = |s_i|^2.
-template <int PT>
+// the costmap terms of shape points j0, j0 + js, ... below P.
+//
+// With e = pose - o, the heading u = (cos, sin) and its normal v, a shape
+// point with body offset (a, b) gives
+//   h = |e + a u + b v|^2 - r^2 = (|e|^2 - r^2) + (a^2 + 2a e.u) + (b^2 + 2b e.v).
+// The fixed-P tiles use the layout of the paper's bodies (the host checks it):
+// * vehicle, the corners and side midpoints of a rectangle: the two terms
+//   take only the values for a = +-alpha, 0 and b = +-beta, 0, so one
+//   obstacle costs 20 operations for its 8 pairs;
+// * quadrotors, every point on the body axis (b = 0): h = |e|^2 - r^2 +
+//   fma(2a, e.u, a^2), two operations a pair.
+// The runtime-P tile takes any shape: h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2
+// with d_i the rotated offset, one add and two FMAs a pair.
+// (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
+template <int MODEL, int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
                                                     const float* sb2, const float* ss, float4 pose, int j0, int js,
                                                     bool with_map, float inv_res, float offx, float offy)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
     const float eps = p.h_eps;
-    float tx[PM], ty[PM];       // 2 d_i
-#pragma unroll
-    for (int i = 0; i < PM; ++i) {
-        tx[i] = fmaf(sa2[i], pose.z, -sb2[i] * pose.w);
-        ty[i] = fmaf(sa2[i], pose.w, sb2[i] * pose.z);
-    }
+    const float cs = pose.z, sn = pose.w;
     float acc = 0.0f, acc2 = 0.0f;
     const int J = p.J;
+    if constexpr (PT != 0 && MODEL == MPPI_CAR) {
+        static_assert(PT == 8, "vehicle layout: 8 points");
+        const float A2 = sa2[0], B2 = sb2[0], AA = ss[4], BB = ss[6];
 #pragma unroll 2
-    for (int j = j0; j < J; j += js) {
-        const float4 o = L.obs[j];
-        const float ex = pose.x - o.x, ey = pose.y - o.y;
-        const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
-        if constexpr (PT != 0) {
+        for (int j = j0; j < J; j += js) {
+            const float4 o = L.obs[j];
+            const float ex = pose.x - o.x, ey = pose.y - o.y;
+            const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+            const float pu = fmaf(ex, cs, ey * sn), pv = fmaf(ey, cs, -ex * sn);
+            const float ep = ee + fmaf(A2, pu, AA), em = ee + fmaf(-A2, pu, AA);
+            const float gp = fmaf(B2, pv, BB), gm = fmaf(-B2, pv, BB);
+            float h[8] = {ep + gp, ep + gm, em + gp, em + gm, ep, em, ee + gp, ee + gm};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
+            reciprocal_sum<8>(h, acc, acc2);
+        }
+    } else if constexpr (PT != 0) {
+#pragma unroll 2
+        for (int j = j0; j < J; j += js) {
+            const float4 o = L.obs[j];
+            const float ex = pose.x - o.x, ey = pose.y - o.y;
+            const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+            const float pu = fmaf(ex, cs, ey * sn);
             float h[PM];
 #pragma unroll
-            for (int i = 0; i < PM; ++i) h[i] = clamp_h(fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])), eps);
+            for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ss[i]), eps);
             reciprocal_sum<PM>(h, acc, acc2);
-        } else {
+        }
+    } else {
+        float tx[PM], ty[PM];       // 2 d_i
+#pragma unroll
+        for (int i = 0; i < PM; ++i) {
+            tx[i] = fmaf(sa2[i], cs, -sb2[i] * sn);
+            ty[i] = fmaf(sa2[i], sn, sb2[i] * cs);
+        }
+#pragma unroll 2
+        for (int j = j0; j < J; j += js) {
+            const float4 o = L.obs[j];
+            const float ex = pose.x - o.x, ey = pose.y - o.y;
+            const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
 #pragma unroll
             for (int i = 0; i < PM; ++i) {
                 if (i < P) acc += __builtin_amdgcn_rcpf(clamp_h(fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])), eps));
@@ -515,7 +549,8 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 #pragma unroll
         for (int i = 0; i < PM; ++i) {
             if ((PT || i < P) && i % js == j0) {
-                const float px = fmaf(0.5f, tx[i], pose.x), py = fmaf(0.5f, ty[i], pose.y);
+                const float px = pose.x + 0.5f * fmaf(sa2[i], cs, -sb2[i] * sn);
+                const float py = pose.y + 0.5f * fmaf(sa2[i], sn, sb2[i] * cs);
                 acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
                                    eps);
             }
@@ -765,8 +800,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = 0.0f;
             if (item < items)
-                part = fused_barrier_pose<PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map, inv_res, offx,
-                                              offy);
+                part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map, inv_res,
+                                                     offx, offy);
             for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             if (sp == 0 && item < items) bv[item] = part;
         };
@@ -1251,7 +1286,7 @@ template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
+    if (p.P == PD && p.shape_kind) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
     else rollout_tile<MODEL, S, 0, false>(p, tile, xs, smem);
 }
 
@@ -1362,7 +1397,7 @@ template <int MODEL, int S>
 hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    if (p.P == PD && p.shape_kind) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     else hipLaunchKernelGGL((k_rollout<MODEL, S, 0>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     return hipGetLastError();
 }

@@ -136,6 +136,23 @@ def test_iteration_matches_oracle(name, make):
     _one_iteration(make())
 
 
+def test_both_barrier_forms_match_oracle():
+    """The fixed-P tiles use the layout of the paper's bodies (rectangle
+    corners and side midpoints; points on the quadrotor's axis); any other
+    shape runs on the runtime-P tile.  Both forms match the oracle, and the
+    same vehicle point set in another order gives the same costs."""
+    wl = W.car(K=700, T=17, J=30)
+    g_fixed, _, _ = _one_iteration(wl)
+    wl_rev = dict(wl, params=dict(wl["params"], shape=wl["params"]["shape"][::-1]))
+    g_rev, ref_rev, _ = _one_iteration(wl_rev)
+    bound = TOL_S * np.maximum(np.abs(ref_rev["S"]), 1.0) + DP * ref_rev["sens"]
+    assert np.all(np.abs(g_rev["S"] - g_fixed["S"]) <= 2.0 * bound)
+    wq = W.quad_small(K=500, T=13, J=20, model="quad5")
+    _one_iteration(wq)
+    off_axis = [[a, 0.01 * (i % 2)] for i, (a, _) in enumerate(wq["params"]["shape"])]
+    _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))
+
+
 @pytest.mark.parametrize("S", [16, 32, 64, 128, 256])
 def test_every_tile_shape_matches_oracle(S):
     _one_iteration(W.quad_small(K=300, T=11, J=13), tile_samples=S)
