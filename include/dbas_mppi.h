@@ -78,6 +78,11 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *  - h_eps > 0: the barrier is B(h) = 1/max(h, h_eps).
  *  - Q, Qf: diagonal running and terminal weights on (x - x_ref).
  *  - shape[P][2]: body-frame shape points (along the heading, normal to it).
+ *    The bodies of Sec. V run a faster form of the barrier: for the vehicle,
+ *    8 points at the corners and side midpoints of a centred rectangle, in
+ *    the order (a,b), (a,-b), (-a,b), (-a,-b), (a,0), (-a,0), (0,b), (0,-b);
+ *    for the quadrotors, 7 points on the body axis (second coordinate 0).
+ *    Any other shape is accepted and computed in the general form.
  *  - u_min/u_max: actuator limits, applied inside the dynamics.
  *  - h_eps in [1e-9, 1e6].
  *  - tile_samples: samples per rollout workgroup (16, 32, 64, 128 or 256);
