@@ -158,6 +158,8 @@ typedef struct mppi_step_info {
     int32_t tiles;                 /* sample tiles per iteration */
     float S_e;                     /* exploration rate the next iteration samples with */
     float cost_b;                  /* C_B of the last U* (adaptive_explore only, else 0) */
+    int32_t barrier_form;          /* 1: the layout form of Sec. V's bodies (see shape), 0: the general form */
+    int32_t reserved;
 } mppi_step_info;
 
 typedef struct mppi_ctrl mppi_t;

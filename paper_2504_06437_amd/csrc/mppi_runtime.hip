@@ -807,6 +807,8 @@ extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
     info->tiles = h->p.tiles;
     info->S_e = st.S_e;
     info->cost_b = st.cost_b;
+    info->barrier_form = h->p.shape_kind;
+    info->reserved = 0;
     return MPPI_OK;
 }
 

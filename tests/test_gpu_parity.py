@@ -142,15 +142,17 @@ def test_both_barrier_forms_match_oracle():
     shape runs on the runtime-P tile.  Both forms match the oracle, and the
     same vehicle point set in another order gives the same costs."""
     wl = W.car(K=700, T=17, J=30)
-    g_fixed, _, _ = _one_iteration(wl)
+    g_fixed, _, info = _one_iteration(wl)
+    assert info["barrier_form"] == 1
     wl_rev = dict(wl, params=dict(wl["params"], shape=wl["params"]["shape"][::-1]))
-    g_rev, ref_rev, _ = _one_iteration(wl_rev)
+    g_rev, ref_rev, info = _one_iteration(wl_rev)
+    assert info["barrier_form"] == 0
     bound = TOL_S * np.maximum(np.abs(ref_rev["S"]), 1.0) + DP * ref_rev["sens"]
     assert np.all(np.abs(g_rev["S"] - g_fixed["S"]) <= 2.0 * bound)
     wq = W.quad_small(K=500, T=13, J=20, model="quad5")
-    _one_iteration(wq)
+    assert _one_iteration(wq)[2]["barrier_form"] == 1
     off_axis = [[a, 0.01 * (i % 2)] for i, (a, _) in enumerate(wq["params"]["shape"])]
-    _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))
+    assert _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))[2]["barrier_form"] == 0
 
 
 @pytest.mark.parametrize("S", [16, 32, 64, 128, 256])
