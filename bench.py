@@ -300,21 +300,37 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"FP64, single thread, {el:.1f} s"}
 
 
+def _kernel_digest() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def _load_record(name: str, kernel: str, workload: str):
+    """A counter record from profiles/<name>, if it was taken on the current
+    kernel source."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+    except (OSError, ValueError):
+        return None
+    r = rec.get(kernel, {}).get(workload)
+    if not r or r.get("kernel_source_sha256_16") != _kernel_digest():
+        return None
+    return r
+
+
 def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch measured by rocprofv3 counters, if recorded for
     the current kernel source (profiles/traffic.json)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
-    src = os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")
-    import hashlib
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    r = rec.get(kernel, {}).get(workload)
-    if not r or r.get("kernel_source_sha256_16") != digest:
-        return None
-    return r.get("bytes_per_launch")
+    r = _load_record("traffic.json", kernel, workload)
+    return r.get("bytes_per_launch") if r else None
+
+
+def load_counters(kernel: str, workload: str):
+    """VALU figures from rocprofv3 SQ counters, if recorded for the current
+    kernel source (profiles/counters.json)."""
+    r = _load_record("counters.json", kernel, workload)
+    return {k: r[k] for k in ("valu_busy", "valu_insts_per_wave", "wait_frac")} if r else None
 
 
 def copy_calibration(mib: int, copies: int = 5):
@@ -381,6 +397,48 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     return rec["rollout"][workload]
 
 
+def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
+    """VALU use of the rollout from SQ counters (two rocprofv3 passes).  Every
+    wave lives for the whole launch (one tile per CU, four waves per SIMD), so
+    a SIMD's VALU busy fraction is the VALU-active time of its waves over one
+    wave's lifetime: SQ_ACTIVE_INST_VALU / (SQ_WAVE_CYCLES / 4)."""
+    act, n, names = _pmc_mean(sq1_dir, "SQ_ACTIVE_INST_VALU", "k_rollout")
+    wcyc, _, _ = _pmc_mean(sq1_dir, "SQ_WAVE_CYCLES", "k_rollout")
+    waves, _, _ = _pmc_mean(sq1_dir, "SQ_WAVES", "k_rollout")
+    insts, _, _ = _pmc_mean(sq1_dir, "SQ_INSTS_VALU", "k_rollout")
+    wait, _, _ = _pmc_mean(sq1_dir, "SQ_WAIT_ANY", "k_rollout")
+    trans, _, _ = _pmc_mean(sq2_dir, "SQ_INSTS_VALU_TRANS_F32", "k_rollout")
+    rec = {}
+    if os.path.exists(out_path):
+        rec = json.load(open(out_path))
+    rec.setdefault("rollout", {})[workload] = {
+        "valu_busy": act / (wcyc / 4.0), "valu_insts_per_wave": insts / waves, "wait_frac": wait / wcyc,
+        "trans_share": trans / insts, "dispatches": n, "kernels": names, "kernel_source_sha256_16": _kernel_digest(),
+    }
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec["rollout"][workload]
+
+
+def update_bytes(p: dict, tiles: int) -> int:
+    """Algorithmic bytes of one update launch: the tile partials N_b (2T rows
+    of `tiles` doubles), the tile scalars (min, normaliser, FP64 flag) read
+    by every workgroup, f_b written once, and U read, U* and the shifted U
+    written."""
+    T, groups = p["T"], (2 * p["T"] + 3) // 4
+    return 16 * T * tiles + groups * 20 * tiles + 8 * tiles + 3 * 8 * T
+
+
+def update_roofline(p: dict, r: dict) -> dict:
+    """The update kernel against HBM: algorithmic bytes per launch over its
+    mean duration (HIP events around the same sampled launches)."""
+    b = update_bytes(p, r["tiles"])
+    gbs = b / (r["update_ms_mean"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "bytes_per_launch": b, "kernel_ms_mean": r["update_ms_mean"],
+            "note": f"latency-bound: {b / 1e6:.2f} MB over {(2 * p['T'] + 3) // 4} workgroups"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,10 +453,19 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("SQ1", "SQ2"),
+                    help="rocprofv3 SQ counter folders -> profiles/counters.json (no GPU use)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders -> profiles/traffic.json (no GPU use)")
     ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     args = ap.parse_args()
+    if args.summarize_counters:
+        wl = W.car()
+        p = wl["params"]
+        workload = f"ground vehicle K={p['K']} T={p['T']} J={len(wl['obstacles'])} P={len(p['shape'])}"
+        print(json.dumps(summarize_counters(*args.summarize_counters, workload,
+                                            os.path.join(ROOT, "profiles", "counters.json")), indent=1))
+        return
     if args.summarize_traffic:
         wl = W.car()
         p = wl["params"]
@@ -434,7 +501,9 @@ def main():
                      "traffic": load_traffic("rollout", workload),
                      "kernel": "rollout", "kernel_ms_mean": r["rollout_ms_mean"],
                      "update_kernel_ms_mean": r["update_ms_mean"], "flops_per_launch": flops,
-                     "launches_timed": r["profiled"], "timed_every": PROFILE_EVERY},
+                     "launches_timed": r["profiled"], "timed_every": PROFILE_EVERY,
+                     "valu": load_counters("rollout", workload)},
+        "update_roofline": update_roofline(p, r),
         "latency_ms": {"plain_p50": r["latency_ms"]["p50"], "plain_p99": r["latency_ms"]["p99"],
                        "n": r["latency_ms"]["n"], "note": "host state in, u0 out (PCIe-inclusive)"},
         "timing": {"wall_s": r["wall_s"], "event_ms": r["event_ms"]},
