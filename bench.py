@@ -300,10 +300,17 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"FP64, single thread, {el:.1f} s"}
 
 
-def _kernel_digest() -> str:
+def _kernel_digest(text: str | None = None) -> str:
+    """SHA-256 (16 hex digits) of the kernel source's code: comments removed
+    and whitespace collapsed, so that a comment edit keeps the records."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    import re
+    if text is None:
+        text = open(os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")).read()
+    code = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    code = re.sub(r"//[^\n]*", " ", code)
+    code = " ".join(code.split())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def _load_record(name: str, kernel: str, workload: str):
@@ -373,15 +380,13 @@ def _pmc_mean(csv_dir: str, counter: str, kernel_substr: str):
 def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, workload, out_path):
     """HBM bytes per rollout launch from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by true bytes / counter reading of a plain copy."""
-    import hashlib
     cf, _, cnames = _pmc_mean(copy_fetch_dir, "FETCH_SIZE", "copy")
     cw, _, _ = _pmc_mean(copy_write_dir, "WRITE_SIZE", "copy")
     f_scale = copy_bytes / (cf * 1024.0)
     w_scale = copy_bytes / (cw * 1024.0)
     fk, nf, names = _pmc_mean(fetch_dir, "FETCH_SIZE", "k_rollout")
     wk, nw, _ = _pmc_mean(write_dir, "WRITE_SIZE", "k_rollout")
-    src = os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = _kernel_digest()
     fetch_b, write_b = fk * 1024.0 * f_scale, wk * 1024.0 * w_scale
     rec = {}
     if os.path.exists(out_path):

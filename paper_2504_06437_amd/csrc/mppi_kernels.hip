@@ -561,7 +561,10 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 
 // ---------------------------------------------------------------------------
 // One tile of S samples: rollout and the tile's softmax partials.
-// PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX).
+// PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX; the
+// fixed-P tiles use the layout form of the paper's bodies).  SC: share the
+// barrier units out by SIMD (the standalone kernel) rather than from one LDS
+// counter (the batched kernel); see barrier_chunk.
 //
 // The horizon is cut into chunks of tc steps that flow through a pipeline of
 // workgroup-wide stages.  In stage k:
@@ -569,9 +572,9 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 //     recursion over chunk k-2 and then integrate the dynamics of chunk k --
 //     the two sequential parts, one lane per sample;
 //   * the other waves draw the noise and inputs of chunk k+1;
-//   * then every wave takes units of the fused-barrier work of chunk k-1 from
-//     an LDS work counter (a wave that owns samples joins when its sequential
-//     part is done).
+//   * then the pool waves take units of the fused-barrier work of chunk k-1
+//     (with the LDS counter, the owner waves join when their sequential part
+//     is done).
 // Every (step, sample) of a chunk is split over nsp adjacent lanes; lane sp
 // of the group takes obstacles sp, sp + nsp, ..., so a wave's lanes read one
 // contiguous run of obstacles at a time; the nsp partial sums meet by wave
