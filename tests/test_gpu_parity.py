@@ -155,6 +155,22 @@ def test_both_barrier_forms_match_oracle():
     assert _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))[2]["barrier_form"] == 0
 
 
+def test_degenerate_and_largest_sizes_match_oracle():
+    """One sample, one step, one obstacle and a one-point body; one step with
+    no obstacle; the most obstacles (MPPI_JMAX = 2048); the longest horizon
+    (MPPI_TMAX = 1024), whose noise does not fit in LDS and is drawn again in
+    the epilogue."""
+    wl = W.car(K=1, T=1, J=1)
+    _one_iteration(dict(wl, params=dict(wl["params"], shape=[[1.0, 0.5]])))
+    _one_iteration(_no_obstacles(W.quad_small(K=64, T=1, J=1)))
+    _one_iteration(W.car(K=20, T=2, J=2048))
+    _one_iteration(W.car(K=16, T=1024, J=3), tile_samples=16)
+
+
+def _no_obstacles(wl):
+    return dict(wl, obstacles=np.zeros((0, 3), dtype=np.float32))
+
+
 @pytest.mark.parametrize("S", [16, 32, 64, 128, 256])
 def test_every_tile_shape_matches_oracle(S):
     _one_iteration(W.quad_small(K=300, T=11, J=13), tile_samples=S)
