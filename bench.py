@@ -206,7 +206,7 @@ def bench_batched(n_ctrl=64, steps=30, seed=3):
     }
 
 
-def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 << 20, streams=2):
+def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 << 20, streams=3):
     """Poisson request streams from `n_robots` robots (sizes as the mixed
     batch) at `rate_hz` each, closed loop through the host plant, served by the
     continuous-batching server.  Latency = completion - scheduled arrival, so

@@ -261,7 +261,7 @@ class Server:
     """Continuous-batching server: robots with resident state, requests
     admitted by launch slots and a device-memory budget for sample scratch."""
 
-    def __init__(self, budget_bytes: int = 256 << 20, max_slots: int = 256, streams: int = 2,
+    def __init__(self, budget_bytes: int = 256 << 20, max_slots: int = 256, streams: int = 3,
                  max_batch: int = 64, device: int = 0):
         self.L = A.load()
         cfg = A.ServerConfig()
