@@ -472,9 +472,10 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
     return make_float2(acc_a, acc_b);
 }
 
-// Part of the fused barrier of one pose: every shape point against obstacles
-// j0, j0 + js, j0 + 2 js, ... below J (read from LDS), plus, with a costmap,
-// the costmap terms of shape points j0, j0 + js, ... below P.
+// Part of the fused barrier of one pose, lane sp of a group of js = 2^lg
+// lanes: every shape point against obstacles sp, sp + js, sp + 2 js, ...
+// below J (read from LDS), plus, with a costmap, the costmap terms of shape
+// points sp, sp + js, ... below P.
 //
 // With e = pose - o, the heading u = (cos, sin) and its normal v, a shape
 // point with body offset (a, b) gives
@@ -490,20 +491,37 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
 template <int MODEL, int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
-                                                    const float* sb2, const float* ss, float4 pose, int j0, int js,
+                                                    const float* sb2, const float* ss, float4 pose, int sp, int lg,
                                                     bool with_map, float inv_res, float offx, float offy)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
     const float eps = p.h_eps;
     const float cs = pose.z, sn = pose.w;
     float acc = 0.0f, acc2 = 0.0f;
-    const int J = p.J;
+    const int J = p.J, js = 1 << lg;
+    // Lane sp of its group of js takes obstacles sp, sp + js, ...: q of them
+    // on every lane, and one more when sp < rem.  The loop count q is the
+    // same on every lane, so the loop is counted in scalar registers; both
+    // reads of a pair are issued before either obstacle is used.
+    const int q = J >> lg, rem = J & (js - 1);
+    auto run = [&](auto&& body) __attribute__((always_inline)) {
+        const float4* ob = L.obs + sp;
+        for (int i = 0; i + 2 <= q; i += 2) {
+            const float4 o0 = ob[0], o1 = ob[js];
+            ob += 2 * js;
+            body(o0);
+            body(o1);
+        }
+        if (q & 1) {
+            body(ob[0]);
+            ob += js;
+        }
+        if (sp < rem) body(ob[0]);
+    };
     if constexpr (PT != 0 && MODEL == MPPI_CAR) {
         static_assert(PT == 8, "vehicle layout: 8 points");
         const float A2 = sa2[0], B2 = sb2[0], AA = ss[4], BB = ss[6];
-#pragma unroll 2
-        for (int j = j0; j < J; j += js) {
-            const float4 o = L.obs[j];
+        run([&](const float4 o) __attribute__((always_inline)) {
             const float ex = pose.x - o.x, ey = pose.y - o.y;
             const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
             const float pu = fmaf(ex, cs, ey * sn), pv = fmaf(ey, cs, -ex * sn);
@@ -513,11 +531,9 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 #pragma unroll
             for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
             reciprocal_sum<8>(h, acc, acc2);
-        }
+        });
     } else if constexpr (PT != 0) {
-#pragma unroll 2
-        for (int j = j0; j < J; j += js) {
-            const float4 o = L.obs[j];
+        run([&](const float4 o) __attribute__((always_inline)) {
             const float ex = pose.x - o.x, ey = pose.y - o.y;
             const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
             const float pu = fmaf(ex, cs, ey * sn);
@@ -525,7 +541,7 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 #pragma unroll
             for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ss[i]), eps);
             reciprocal_sum<PM>(h, acc, acc2);
-        }
+        });
     } else {
         float tx[PM], ty[PM];       // 2 d_i
 #pragma unroll
@@ -533,22 +549,20 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             tx[i] = fmaf(sa2[i], cs, -sb2[i] * sn);
             ty[i] = fmaf(sa2[i], sn, sb2[i] * cs);
         }
-#pragma unroll 2
-        for (int j = j0; j < J; j += js) {
-            const float4 o = L.obs[j];
+        run([&](const float4 o) __attribute__((always_inline)) {
             const float ex = pose.x - o.x, ey = pose.y - o.y;
             const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
 #pragma unroll
             for (int i = 0; i < PM; ++i) {
                 if (i < P) acc += __builtin_amdgcn_rcpf(clamp_h(fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])), eps));
             }
-        }
+        });
     }
     acc += acc2;
     if (with_map) {
 #pragma unroll
         for (int i = 0; i < PM; ++i) {
-            if ((PT || i < P) && i % js == j0) {
+            if ((PT || i < P) && (i & (js - 1)) == sp) {
                 const float px = pose.x + 0.5f * fmaf(sa2[i], cs, -sb2[i] * sn);
                 const float py = pose.y + 0.5f * fmaf(sa2[i], sn, sb2[i] * cs);
                 acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
@@ -803,7 +817,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = 0.0f;
             if (item < items)
-                part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, nsp, has_map, inv_res,
+                part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res,
                                                      offx, offy);
             for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             if (sp == 0 && item < items) bv[item] = part;
