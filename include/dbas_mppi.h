@@ -81,8 +81,9 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *    The bodies of Sec. V run a faster form of the barrier: for the vehicle,
  *    8 points at the corners and side midpoints of a centred rectangle, in
  *    the order (a,b), (a,-b), (-a,b), (-a,-b), (a,0), (-a,0), (0,b), (0,-b);
- *    for the quadrotors, 7 points on the body axis (second coordinate 0).
- *    Any other shape is accepted and computed in the general form.
+ *    for the quadrotors, 7 points on the body axis (second coordinate 0),
+ *    faster still when points 0, 1, 2 mirror points 6, 5, 4 about the
+ *    centre.  Any other shape is accepted and computed in the general form.
  *  - u_min/u_max: actuator limits, applied inside the dynamics.
  *  - h_eps in [1e-9, 1e6].
  *  - tile_samples: samples per rollout workgroup (16, 32, 64, 128 or 256);
@@ -158,7 +159,7 @@ typedef struct mppi_step_info {
     int32_t tiles;                 /* sample tiles per iteration */
     float S_e;                     /* exploration rate the next iteration samples with */
     float cost_b;                  /* C_B of the last U* (adaptive_explore only, else 0) */
-    int32_t barrier_form;          /* 1: the layout form of Sec. V's bodies (see shape), 0: the general form */
+    int32_t barrier_form;          /* 0: the general form; 1: the layout form of Sec. V's bodies (see shape); 2: the quadrotor's mirrored-axis form */
     int32_t reserved;
 } mppi_step_info;
 

@@ -63,7 +63,7 @@ struct DevParams {
     int32_t adaptive;        // 1: S_e follows the barrier cost of U*
     float explore_mu;
     int32_t sgf_m;           // Savitzky-Golay half window (0: no smoothing)
-    int32_t shape_kind;      // 1: the shape has the layout the model's fixed-P tile uses
+    int32_t shape_kind;      // ShapeForm: the layout form the model's fixed-P tile may use
     const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
@@ -150,23 +150,29 @@ UnitGroups group_units(std::vector<BatchWork>& work, BatchUnit* out);
 // the vehicle, 7 for the quadrotors.
 constexpr int fixed_points(int model) { return model == MPPI_CAR ? 8 : 7; }
 
-// Does the shape have the layout the fixed-P tile exploits?  Vehicle: the
-// corners and side midpoints of a rectangle centred on the reference point,
-// in the order (a, b), (a, -b), (-a, b), (-a, -b), (a, 0), (-a, 0), (0, b),
-// (0, -b).  Quadrotors: every point on the body axis (b = 0).
-inline bool shape_has_fixed_layout(int model, int P, const float (*sh)[2])
+// Which layout form of the fixed-P tile the shape allows (0: none; the
+// runtime-P tile's general form is used).  Vehicle, 1: the corners and side
+// midpoints of a rectangle centred on the reference point, in the order
+// (a, b), (a, -b), (-a, b), (-a, -b), (a, 0), (-a, 0), (0, b), (0, -b).
+// Quadrotors, 1: every point on the body axis (b = 0); 2: moreover points
+// 0, 1, 2 are the mirror images of points 6, 5, 4 (a_i = -a_{6-i}).
+enum ShapeForm : int32_t { kShapeGeneral = 0, kShapeLayout = 1, kShapeMirroredAxis = 2 };
+
+inline int32_t shape_form(int model, int P, const float (*sh)[2])
 {
-    if (P != fixed_points(model)) return false;
+    if (P != fixed_points(model)) return kShapeGeneral;
     if (model == MPPI_CAR) {
         const float a = sh[0][0], b = sh[0][1];
         const float want[8][2] = {{a, b}, {a, -b}, {-a, b}, {-a, -b}, {a, 0.0f}, {-a, 0.0f}, {0.0f, b}, {0.0f, -b}};
         for (int i = 0; i < 8; ++i)
-            if (sh[i][0] != want[i][0] || sh[i][1] != want[i][1]) return false;
-        return true;
+            if (sh[i][0] != want[i][0] || sh[i][1] != want[i][1]) return kShapeGeneral;
+        return kShapeLayout;
     }
     for (int i = 0; i < P; ++i)
-        if (sh[i][1] != 0.0f) return false;
-    return true;
+        if (sh[i][1] != 0.0f) return kShapeGeneral;
+    for (int i = 0; i < 3; ++i)
+        if (sh[i][0] != -sh[6 - i][0]) return kShapeLayout;
+    return kShapeMirroredAxis;
 }
 
 inline int state_dim(int model) { return model == MPPI_QUAD6 ? 6 : model == MPPI_QUAD5 ? 5 : 4; }

@@ -485,7 +485,8 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 //   take only the values for a = +-alpha, 0 and b = +-beta, 0, so one
 //   obstacle costs 20 operations for its 8 pairs;
 // * quadrotors, every point on the body axis (b = 0): h = |e|^2 - r^2 +
-//   fma(2a, e.u, a^2), two operations a pair.
+//   fma(2a, e.u, a^2), two operations a pair; when the points mirror about
+//   the centre (the paper's frame), a mirrored pair takes three operations.
 // The runtime-P tile takes any shape: h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2
 // with d_i the rotated offset, one add and two FMAs a pair.
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
@@ -533,15 +534,34 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             reciprocal_sum<8>(h, acc, acc2);
         });
     } else if constexpr (PT != 0) {
-        run([&](const float4 o) __attribute__((always_inline)) {
-            const float ex = pose.x - o.x, ey = pose.y - o.y;
-            const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
-            const float pu = fmaf(ex, cs, ey * sn);
-            float h[PM];
+        static_assert(PT == 7, "quadrotor layout: 7 points");
+        if (p.shape_kind == kShapeMirroredAxis) {
+            // a_{6-i} = -a_i: the pair shares |e|^2 - r^2 + a_i^2, and its two
+            // points differ in the sign of 2 a_i e.u
+            const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], S0 = ss[0], S1 = ss[1], S2 = ss[2];
+            const float AM = sa2[3], SM = ss[3];
+            run([&](const float4 o) __attribute__((always_inline)) {
+                const float ex = pose.x - o.x, ey = pose.y - o.y;
+                const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+                const float pu = fmaf(ex, cs, ey * sn);
+                const float b0 = ee + S0, b1 = ee + S1, b2 = ee + S2;
+                float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), ee + fmaf(AM, pu, SM),
+                              fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
 #pragma unroll
-            for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ss[i]), eps);
-            reciprocal_sum<PM>(h, acc, acc2);
-        });
+                for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
+                reciprocal_sum<7>(h, acc, acc2);
+            });
+        } else {
+            run([&](const float4 o) __attribute__((always_inline)) {
+                const float ex = pose.x - o.x, ey = pose.y - o.y;
+                const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+                const float pu = fmaf(ex, cs, ey * sn);
+                float h[PM];
+#pragma unroll
+                for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ss[i]), eps);
+                reciprocal_sum<PM>(h, acc, acc2);
+            });
+        }
     } else {
         float tx[PM], ty[PM];       // 2 d_i
 #pragma unroll
@@ -1303,7 +1323,7 @@ template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD && p.shape_kind) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
+    if (p.P == PD && p.shape_kind != kShapeGeneral) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
     else rollout_tile<MODEL, S, 0, false>(p, tile, xs, smem);
 }
 
@@ -1414,7 +1434,7 @@ template <int MODEL, int S>
 hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD && p.shape_kind) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    if (p.P == PD && p.shape_kind != kShapeGeneral) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     else hipLaunchKernelGGL((k_rollout<MODEL, S, 0>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     return hipGetLastError();
 }

@@ -419,7 +419,7 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
         p.Qf[a] = a < n ? cfg->Qf[a] : 0.0f;
     }
     std::memcpy(p.shape, cfg->shape, sizeof p.shape);
-    p.shape_kind = shape_has_fixed_layout(p.model, p.P, p.shape) ? 1 : 0;
+    p.shape_kind = shape_form(p.model, p.P, p.shape);
     p.export_noise = cfg->export_noise ? 1 : 0;
     p.adaptive = cfg->adaptive_explore ? 1 : 0;
     p.explore_mu = cfg->explore_mu;

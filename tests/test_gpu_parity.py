@@ -138,9 +138,10 @@ def test_iteration_matches_oracle(name, make):
 
 def test_both_barrier_forms_match_oracle():
     """The fixed-P tiles use the layout of the paper's bodies (rectangle
-    corners and side midpoints; points on the quadrotor's axis); any other
-    shape runs on the runtime-P tile.  Both forms match the oracle, and the
-    same vehicle point set in another order gives the same costs."""
+    corners and side midpoints; points on the quadrotor's axis, mirrored
+    about its centre or not); any other shape runs on the runtime-P tile.
+    Every form matches the oracle, and the same point set in another order
+    gives the same costs."""
     wl = W.car(K=700, T=17, J=30)
     g_fixed, _, info = _one_iteration(wl)
     assert info["barrier_form"] == 1
@@ -150,8 +151,17 @@ def test_both_barrier_forms_match_oracle():
     bound = TOL_S * np.maximum(np.abs(ref_rev["S"]), 1.0) + DP * ref_rev["sens"]
     assert np.all(np.abs(g_rev["S"] - g_fixed["S"]) <= 2.0 * bound)
     wq = W.quad_small(K=500, T=13, J=20, model="quad5")
-    assert _one_iteration(wq)[2]["barrier_form"] == 1
-    off_axis = [[a, 0.01 * (i % 2)] for i, (a, _) in enumerate(wq["params"]["shape"])]
+    g_mirror, _, info = _one_iteration(wq)
+    assert info["barrier_form"] == 2
+    # the same points with the middle one moved off the end of the list: on
+    # the axis, no longer mirrored in the order the mirrored form reads
+    sh = wq["params"]["shape"]
+    moved = [sh[3]] + sh[:3] + sh[4:]
+    g_axis, ref_axis, info = _one_iteration(dict(wq, params=dict(wq["params"], shape=moved)))
+    assert info["barrier_form"] == 1
+    bound = TOL_S * np.maximum(np.abs(ref_axis["S"]), 1.0) + DP * ref_axis["sens"]
+    assert np.all(np.abs(g_axis["S"] - g_mirror["S"]) <= 2.0 * bound)
+    off_axis = [[a, 0.01 * (i % 2)] for i, (a, _) in enumerate(sh)]
     assert _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))[2]["barrier_form"] == 0
 
 
