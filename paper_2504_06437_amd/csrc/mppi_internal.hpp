@@ -64,6 +64,7 @@ struct DevParams {
     float explore_mu;
     int32_t sgf_m;           // Savitzky-Golay half window (0: no smoothing)
     int32_t shape_kind;      // ShapeForm: the layout form the model's fixed-P tile may use
+    double beta_d_weight;    // R_B sum_{t=1..T} c_t / beta_d, the common barrier-state cost per unit of beta_d
     const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
@@ -193,7 +194,7 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
-    b += 64;                                    // pool waves per SIMD, owner SIMD, cshift
+    b += 64;                                    // pool waves per SIMD, owner SIMD, unit counters
     return b;
 }
 

@@ -361,7 +361,7 @@ struct TileLds {
     double* e;        // [kMaxTile] tile exponentials
     double* slots;    // [16] block-reduction slots
     int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
-                      // cshift (double, at byte 32)
+                      // [5], [6] the batched kernel's unit counters
     // chunk slots, two buffers each (buffer b at offset b * cs):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, 0)
     float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
@@ -704,8 +704,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // -beta_d gamma_B/(1-gamma_B) (T - gamma_B (1-gamma_B^T)/(1-gamma_B)).
     // The common part's cost R_B sum_t c_t is the same for every sample and is
     // added in FP64 (cshift), so a large beta_d cannot swamp the FP32 sums;
-    // one lane of the noise pool forms it during the second stage and leaves
-    // it in LDS.
+    // the host forms its factor R_B sum_t c_t / beta_d once per controller.
     float beta = 0.0f;
     float S_hi = 0.0f, S_lo = 0.0f;
 
@@ -786,6 +785,35 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
+    // Split of the fused-barrier items of a chunk of `items` (step, sample)
+    // items over nsp = 2^lg lanes each: among the splits that give every wave
+    // of the noise pool a unit, the one whose units, spread over the CU's
+    // SIMDs, cost least: ceil(units / SIMDs) units, each of ceil(J / nsp)
+    // obstacles x P pairs plus a fixed part (pose, shape transform,
+    // reduction: about 8 pairs' worth).  Without such a split, the finest.
+    auto split_lg = [&](int items) {
+        int lg = 0;
+        long best = -1;
+        for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
+            const long units = ((long)(items << l) + kWave - 1) / kWave;
+            if (units < kRollWaves - DW) {
+                if (best < 0) lg = l;                    // the finest so far
+                continue;
+            }
+            const long per_lane = (J + (1 << l) - 1) >> l;
+            const long cost = (units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8);
+            if (best < 0 || cost < best) {
+                best = cost;
+                lg = l;
+            }
+        }
+        return lg;
+    };
+    // A tile's chunks have at most three lengths (the first, the middle ones,
+    // the last), so their splits are chosen once, packed 4 bits each.
+    const int lg_pack = split_lg(chunk_len(0) * S) | (nch > 2 ? split_lg(tc * S) << 4 : 0) |
+                        (nch > 1 ? split_lg(chunk_len(nch - 1) * S) << 8 : 0);
+
     // Fused barrier of every (step, sample) of chunk c, in units of one wave.
     // With SC the units are shared out by SIMD, not taken first come first
     // served: a SIMD's older waves win the issue arbitration, so under a
@@ -800,34 +828,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // counter.  Which wave computes a unit never changes its arithmetic.
     auto barrier_chunk = [&](int c) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
-        // split: among the splits that give every wave of the noise pool a
-        // unit, the one whose units, spread over the CU's SIMDs, cost least:
-        // ceil(units / SIMDs) units, each of ceil(J / nsp) obstacles x P
-        // pairs plus a fixed part (pose, shape transform, reduction: about 8
-        // pairs' worth).  Without such a split, the finest one.
-        int lg = 0;
-        {
-            long best = -1;
-            for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
-                const long units = ((long)(items << l) + kWave - 1) / kWave;
-                lg = l;                                  // the finest so far
-                if (units < kRollWaves - DW) continue;
-                const long per_lane = (J + (1 << l) - 1) >> l;
-                const long cost = (units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8);
-                if (best < 0 || cost < best) best = cost;
-            }
-            if (best >= 0) {
-                for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
-                    const long units = ((long)(items << l) + kWave - 1) / kWave;
-                    if (units < kRollWaves - DW) continue;
-                    const long per_lane = (J + (1 << l) - 1) >> l;
-                    if ((units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8) == best) {
-                        lg = l;
-                        break;
-                    }
-                }
-            }
-        }
+        const int lg = (lg_pack >> (c == 0 ? 0 : c == nch - 1 ? 8 : 4)) & 15;
         const int nsp = 1 << lg;
         const int units = ((items << lg) + kWave - 1) / kWave;
         const float4* pz = L.pose + (c & 1) * L.cs;
@@ -895,18 +896,11 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             if (owner && st_k < nch) dynamics_chunk(st_k);
         } else {
             if (st_k + 1 < nch) inputs_chunk(st_k + 1, POOL0);
-            if (st_k == 1 && tid == POOL0) {
-                const double g = (double)p.gamma_b;
-                const double geo = g * (1.0 - pow(g, (double)T)) / (1.0 - g);
-                *reinterpret_cast<double*>(L.work + 8) =
-                    (double)p.r_b * (-(double)beta_d * g / (1.0 - g) * ((double)T - geo));
-            }
         }
         if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1);
         lds_barrier();
     }
-    // (the stage loop always runs stage 1, which wrote it)
-    const double cshift = *reinterpret_cast<const double*>(L.work + 8);
+    const double cshift = (double)beta_d * p.beta_d_weight;
     if (owner) {
         const float* rf = L.ref + T * NS;
         float phi = 0.0f;

@@ -413,6 +413,14 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     p.gamma_u = cfg->gamma_u;
     p.gamma_b = cfg->gamma_b;
     p.r_b = cfg->r_b;
+    {
+        // the common part c_t = gamma_B (c_{t-1} - beta_d), c_0 = 0, of the
+        // barrier state sums over t = 1..T to -beta_d gamma_B/(1-gamma_B)
+        // (T - gamma_B (1 - gamma_B^T)/(1 - gamma_B)); its cost is R_B times that
+        const double g = (double)cfg->gamma_b;
+        const double geo = g * (1.0 - std::pow(g, (double)cfg->T)) / (1.0 - g);
+        p.beta_d_weight = -(double)cfg->r_b * g / (1.0 - g) * ((double)cfg->T - geo);
+    }
     p.h_eps = cfg->h_eps;
     for (int a = 0; a < MPPI_NMAX; ++a) {
         p.Q[a] = a < n ? cfg->Q[a] : 0.0f;
