@@ -83,11 +83,12 @@ __device__ __forceinline__ float2 nln_pair(uint4 r, float scale0, float scale1, 
     return o;
 }
 
-// sin and cos of a heading.  Cody-Waite reduction by pi/2 (three-part split
-// of pi/2, each product exact inside an FMA) to |r| <= pi/4, then the Taylor
-// series of sin to r^9 and of cos to r^10 (truncation < 3e-9 on |r| <= pi/4,
-// below half an FP32 ulp), and the quadrant's swap and signs.  Headings
-// beyond 4096 quarter turns fall back to the library routine.
+// sin and cos of an angle (a heading, a steering angle).  Cody-Waite
+// reduction by pi/2 (three-part split of pi/2, each product exact inside an
+// FMA) to |r| <= pi/4, then the Taylor series of sin to r^9 and of cos to
+// r^10 (truncation < 3e-9 on |r| <= pi/4, below half an FP32 ulp), and the
+// quadrant's swap and signs.  Angles beyond 4096 quarter turns fall back to
+// the library routine.
 __device__ __forceinline__ void heading_sincos(float x, float& s, float& c)
 {
     const float k = rintf(x * 0.63661975f);
@@ -334,10 +335,12 @@ template <> struct Model<MPPI_QUAD5> {
 template <> struct Model<MPPI_CAR> {
     static constexpr int NS = 4;
     // Sec. V-B Ackermann model: state (x, y, theta, v); inputs (steer, accel).
-    // f0 = tan(phi)/L, f1 = a.
+    // f0 = tan(phi)/L = sin(phi) / (cos(phi) L), f1 = a.
     __device__ static __forceinline__ void inputs(const DevParams& p, float s0, float s1, float& f0, float& f1)
     {
-        f0 = tanf(s0) / p.wheelbase;
+        float sp, cp;
+        heading_sincos(s0, sp, cp);
+        f0 = sp / (cp * p.wheelbase);
         f1 = s1;
     }
     __device__ static __forceinline__ void step(const DevParams& p, float* x, float f0, float f1, float sth, float cth)
@@ -440,12 +443,14 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
                                        float ath, float bx, float by, float bth, float inv_res, float offx,
                                        float offy)
 {
+    const int J = p.J;
+    const int i0 = (int)threadIdx.x - first;
+    // a wave with no obstacle and no costmap point to take is done
+    if ((int)(threadIdx.x & ~(kWave - 1)) - first >= max(J, p.sdf != nullptr ? P : 0)) return make_float2(0.0f, 0.0f);
     float sa, ca, sb, cb;
     heading_sincos(ath, sa, ca);
     heading_sincos(bth, sb, cb);
     float acc_a = 0.0f, acc_b = 0.0f;
-    const int J = p.J;
-    const int i0 = (int)threadIdx.x - first;
     for (int j = i0; j < J; j += kRollBlock - first) {
         const float4 o = L.obs[j];
 #pragma unroll
