@@ -1306,6 +1306,19 @@ __device__ void explore_ctrl(const DevParams& p, const X0& xs, unsigned char* sm
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup i to XCD
+// i mod 8).  The tile of workgroup i makes each XCD take a contiguous run of
+// tiles, so the tiles whose partial sums share a line of the [2T][tiles]
+// layout write it from one L2 (a bijection on [0, tiles) for any count).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int i, int tiles)
+{
+    const int x = i % kXcds, j = i / kXcds;
+    const int q = tiles / kXcds, r = tiles % kXcds;
+    return x * q + min(x, r) + j;
+}
+
 template <int MODEL, int S, int PT>
 __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 {
@@ -1314,7 +1327,7 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 #pragma unroll
     for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0_ptr ? (i < p.n ? a.x0_ptr[i] : 0.0f) : a.x0[i];
     xs.parity = a.parity;
-    rollout_tile<MODEL, S, PT, true>(p, blockIdx.x, xs, smem);
+    rollout_tile<MODEL, S, PT, true>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
 
 __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
