@@ -358,7 +358,8 @@ template <> struct Model<MPPI_CAR> {
 // LDS carve-up of one rollout tile (sizes: tile_fixed_lds, then two chunks of
 // per-(step, sample) slots).
 struct TileLds {
-    float4* obs;      // [J] (ox, oy, -r^2, 0), local frame
+    float4* obs;      // [J] (ox, oy, -r^2 + d, -r^2), local frame; d = |s_0|^2 on the
+                      // vehicle's layout-form tile, else 0
     float2* U;        // [T]
     float* ref;       // [(T+1) n], local frame
     double* e;        // [kMaxTile] tile exponentials
@@ -460,8 +461,8 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
                 const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
                 const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
                 const float dax = pax - o.x, day = pay - o.y, dbx = pbx - o.x, dby = pby - o.y;
-                acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.z)), p.h_eps);
-                acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.z)), p.h_eps);
+                acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.w)), p.h_eps);
+                acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.w)), p.h_eps);
             }
         }
     }
@@ -526,14 +527,18 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
     };
     if constexpr (PT != 0 && MODEL == MPPI_CAR) {
         static_assert(PT == 8, "vehicle layout: 8 points");
-        const float A2 = sa2[0], B2 = sb2[0], AA = ss[4], BB = ss[6];
+        // point 0 is (a, b); o.z = -r^2 + a^2 + b^2, so C = |e|^2 - r^2 + a^2 +
+        // b^2 takes two operations, and with P = 2a e.u, Q = 2b e.v the
+        // corners are (C +- P) +- Q, the side midpoints C +- P - b^2 and
+        // C - a^2 +- Q: 19 operations for the 8 pairs
+        const float AA = ss[4], BB = ss[6];
+        const float cu = sa2[0] * cs, su = sa2[0] * sn, cv = sb2[0] * cs, sv = sb2[0] * sn;
         run([&](const float4 o) __attribute__((always_inline)) {
             const float ex = pose.x - o.x, ey = pose.y - o.y;
-            const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
-            const float pu = fmaf(ex, cs, ey * sn), pv = fmaf(ey, cs, -ex * sn);
-            const float ep = ee + fmaf(A2, pu, AA), em = ee + fmaf(-A2, pu, AA);
-            const float gp = fmaf(B2, pv, BB), gm = fmaf(-B2, pv, BB);
-            float h[8] = {ep + gp, ep + gm, em + gp, em + gm, ep, em, ee + gp, ee + gm};
+            const float C = fmaf(ex, ex, fmaf(ey, ey, o.z));
+            const float Pu = fmaf(ex, cu, ey * su), Qv = fmaf(ey, cv, -ex * sv);
+            const float CP = C + Pu, CM = C - Pu, D = C - AA;
+            float h[8] = {CP + Qv, CP - Qv, CM + Qv, CM - Qv, CP - BB, CM - BB, D + Qv, D - Qv};
 #pragma unroll
             for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
             reciprocal_sum<8>(h, acc, acc2);
@@ -648,9 +653,16 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 
     // ---- staging: local frame centred on the start position ----
     const double ox = (double)xs.v[0], oy = (double)xs.v[1];
-    for (int j = tid; j < J; j += kRollBlock) {
-        const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
-        L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(-(r * r)), 0.0f);
+    {
+        // the vehicle's layout form offsets |e|^2 - r^2 by |s_0|^2 (third word);
+        // the fourth word keeps -r^2 for the start and goal poses' barrier
+        constexpr bool kOffset = PT != 0 && MODEL == MPPI_CAR;
+        const double s00 = (double)p.shape[0][0], s01 = (double)p.shape[0][1];
+        const double d0 = kOffset ? s00 * s00 + s01 * s01 : 0.0;
+        for (int j = tid; j < J; j += kRollBlock) {
+            const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
+            L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(d0 - r * r), (float)(-(r * r)));
+        }
     }
     if (tid < 8) L.work[tid] = 0;
     for (int t = tid; t < T; t += kRollBlock) L.U[t] = make_float2(Uin[2 * t], Uin[2 * t + 1]);
