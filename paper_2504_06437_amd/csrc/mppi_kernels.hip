@@ -359,7 +359,7 @@ template <> struct Model<MPPI_CAR> {
 // per-(step, sample) slots).
 struct TileLds {
     float4* obs;      // [J] (ox, oy, -r^2 + d, -r^2), local frame; d = |s_0|^2 on the
-                      // vehicle's layout-form tile, else 0
+                      // vehicle's layout-form and the quadrotor's mirrored-axis tiles, else 0
     float2* U;        // [T]
     float* ref;       // [(T+1) n], local frame
     double* e;        // [kMaxTile] tile exponentials
@@ -547,15 +547,16 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         static_assert(PT == 7, "quadrotor layout: 7 points");
         if (p.shape_kind == kShapeMirroredAxis) {
             // a_{6-i} = -a_i: the pair shares |e|^2 - r^2 + a_i^2, and its two
-            // points differ in the sign of 2 a_i e.u
-            const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], S0 = ss[0], S1 = ss[1], S2 = ss[2];
-            const float AM = sa2[3], SM = ss[3];
+            // points differ in the sign of 2 a_i e.u.  o.z = -r^2 + a_0^2, so
+            // the first pair's shared term is b0 = |e|^2 + o.z itself.
+            const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
+            const float AM = sa2[3], DM = ss[3] - ss[0];
             run([&](const float4 o) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
-                const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+                const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
-                const float b0 = ee + S0, b1 = ee + S1, b2 = ee + S2;
-                float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), ee + fmaf(AM, pu, SM),
+                const float b1 = b0 + D1, b2 = b0 + D2;
+                float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), b0 + fmaf(AM, pu, DM),
                               fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
 #pragma unroll
                 for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
@@ -654,11 +655,12 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // ---- staging: local frame centred on the start position ----
     const double ox = (double)xs.v[0], oy = (double)xs.v[1];
     {
-        // the vehicle's layout form offsets |e|^2 - r^2 by |s_0|^2 (third word);
-        // the fourth word keeps -r^2 for the start and goal poses' barrier
-        constexpr bool kOffset = PT != 0 && MODEL == MPPI_CAR;
+        // the vehicle's layout form and the quadrotor's mirrored-axis form
+        // offset |e|^2 - r^2 by |s_0|^2 (third word); the fourth word keeps
+        // -r^2 for the start and goal poses' barrier
+        const bool offset = PT != 0 && (MODEL == MPPI_CAR || p.shape_kind == kShapeMirroredAxis);
         const double s00 = (double)p.shape[0][0], s01 = (double)p.shape[0][1];
-        const double d0 = kOffset ? s00 * s00 + s01 * s01 : 0.0;
+        const double d0 = offset ? s00 * s00 + s01 * s01 : 0.0;
         for (int j = tid; j < J; j += kRollBlock) {
             const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
             L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(d0 - r * r), (float)(-(r * r)));
