@@ -11,7 +11,7 @@ timed region: W untimed iterations, then `--steps` iterations issued back to
 back on the controller's stream with the states already in device memory,
 bracketed by device synchronisation.  Also reported:
   * roofline of the rollout kernel (algorithmic FLOPs per launch / its mean
-    duration from HIP events recorded on its stream around every 8th launch
+    duration from HIP events recorded on its stream around every 32nd launch
     of the timed region),
   * p50/p99 control-step latency of the plain path (host state in, u0 out),
   * the quadrotor at scale (K=16384, T=100, 400 obstacles + costmap),
@@ -42,9 +42,9 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "rollout-steps/sec (K·T) and p50/p99 control-step latency, batched vs plain"
 # kernel durations come from HIP events around every PROFILE_EVERY-th
-# iteration of the timed loop (events around every iteration would add a few
-# microseconds to each step)
-PROFILE_EVERY = 8
+# iteration of the timed loop (the events of one iteration add about 9 us to
+# it, so around every iteration they would cost a fifth of the step)
+PROFILE_EVERY = 32
 
 
 def rollout_flops_per_step(params: dict, J: int, with_map: bool) -> float:
@@ -98,7 +98,7 @@ def bench_plain(wl, steps, warmup):
     c = make_controller(wl)
     p = wl["params"]
     K, T = p["K"], p["T"]
-    n_states = max(steps, 200)
+    n_states = 200                      # closed-loop states, cycled through by the timed loop
     states, lat = closed_loop_states(c, wl, n_states)
     lat = lat[min(20, len(lat) // 4):]
     x_dev = hip.DeviceArray.from_numpy(states)
@@ -447,7 +447,7 @@ def update_roofline(p: dict, r: dict) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1024)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
