@@ -741,12 +741,12 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     auto chunk_len = [&](int c) { return c == 0 ? tc0 : min(tc, T - chunk_t0(c)); };
 
     // the noise of sample kk at step t (Sec. IV-C mixture, scaled per Alg. 1)
-    // (the key words pass through an empty asm statement, so that the twenty
-    // round keys are formed per item by scalar adds instead of being held in
-    // scalar registers across the whole stage loop, where they crowded out
-    // other values into reloads)
+    // (the key words, uniform over the tile, pass through an empty asm
+    // statement, so that the twenty round keys are formed per item by scalar
+    // adds instead of being held in scalar registers across the whole stage
+    // loop, where they crowded out other values into reloads)
     auto noise_at = [&](int kk, int t) __attribute__((always_inline)) {
-        uint32_t k0 = p.seed_lo, k1 = p.seed_hi;
+        uint32_t k0 = __builtin_amdgcn_readfirstlane(p.seed_lo), k1 = __builtin_amdgcn_readfirstlane(p.seed_hi);
         asm volatile("" : "+s"(k0), "+s"(k1));
         const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), k0, k1);
         return nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
