@@ -163,6 +163,13 @@ def test_both_barrier_forms_match_oracle():
     assert np.all(np.abs(g_axis["S"] - g_mirror["S"]) <= 2.0 * bound)
     off_axis = [[a, 0.01 * (i % 2)] for i, (a, _) in enumerate(sh)]
     assert _one_iteration(dict(wq, params=dict(wq["params"], shape=off_axis)))[2]["barrier_form"] == 0
+    # other bodies of the same layouts: a 3.4 m x 1.2 m rectangle, and a
+    # mirrored axis whose middle point is off the centre
+    a, b = 1.7, 0.6
+    rect = [[a, b], [a, -b], [-a, b], [-a, -b], [a, 0.0], [-a, 0.0], [0.0, b], [0.0, -b]]
+    assert _one_iteration(dict(wl, params=dict(wl["params"], shape=rect)))[2]["barrier_form"] == 1
+    axis = [[-0.3, 0.0], [-0.2, 0.0], [-0.05, 0.0], [0.02, 0.0], [0.05, 0.0], [0.2, 0.0], [0.3, 0.0]]
+    assert _one_iteration(dict(wq, params=dict(wq["params"], shape=axis)))[2]["barrier_form"] == 2
 
 
 def test_degenerate_and_largest_sizes_match_oracle():
