@@ -1333,13 +1333,37 @@ __device__ __forceinline__ int xcd_tile(int i, int tiles)
     return x * q + min(x, r) + j;
 }
 
+// The kernel's arguments (the parameter block, then the step's arguments)
+// are read field by field through the prologue, and each first touch of one
+// of their lines would wait on memory in turn.  One word of every 64-byte
+// line of the first Bytes bytes is loaded here, all in one batch, so the
+// later loads hit the scalar cache.
+template <int Bytes>
+__device__ __forceinline__ void touch_kernargs()
+{
+    using KWord = const __attribute__((address_space(4))) uint32_t;
+    KWord* kp = (KWord*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < Bytes / 4; i += 16) t ^= kp[i];
+    asm volatile("" ::"s"(t));
+}
+
 template <int MODEL, int S, int PT>
 __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NS = Model<MODEL>::NS;
+    touch_kernargs<(int)(sizeof(DevParams) + sizeof(StepArgs))>();
     X0 xs;
+    if (a.x0_ptr) {
+        // the state's NS words, unconditionally, so the loads issue together
 #pragma unroll
-    for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0_ptr ? (i < p.n ? a.x0_ptr[i] : 0.0f) : a.x0[i];
+        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = i < NS ? a.x0_ptr[i] : 0.0f;
+    } else {
+#pragma unroll
+        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0[i];
+    }
     xs.parity = a.parity;
     rollout_tile<MODEL, S, PT, true>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
