@@ -1,0 +1,115 @@
+"""bench.py's host side: the records behind `roofline.traffic` and
+`roofline.valu` are computed from rocprofv3 counter files as documented,
+keyed by the kernel source's code and ignored once that code changes; the
+algorithmic FLOP count of the vehicle workload; and the one-GPU contract."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+from paper_2504_06437_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WORKLOAD = "ground vehicle K=4096 T=50 J=100 P=8"
+ROLLOUT = "void dbas::(anonymous namespace)::k_rollout<2, 16, 8>(dbas::DevParams, dbas::StepArgs)"
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _counter_csv(folder, rows):
+    """A rocprofv3-style counter_collection.csv: (dispatch, kernel, counter, value)."""
+    os.makedirs(folder, exist_ok=True)
+    with open(os.path.join(folder, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(FIELDS)
+        for r in rows:
+            w.writerow(r)
+
+
+def test_digest_ignores_comments_and_whitespace_only():
+    src = "int f(int a) {\n    return a + 1;   // one more\n}\n/* block\n comment */\n"
+    same = "int f(int a) { return a + 1; }\n// another comment\n"
+    other = "int f(int a) { return a + 2; }\n"
+    assert bench._kernel_digest(src) == bench._kernel_digest(same)
+    assert bench._kernel_digest(src) != bench._kernel_digest(other)
+    assert len(bench._kernel_digest(src)) == 16
+
+
+def test_traffic_summary_scales_counters_by_the_copy(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "_kernel_digest", lambda text=None: "00000000000000aa")
+    copy_bytes = 64 << 20
+    # the copy reads half its bytes in FETCH_SIZE and all of them in WRITE_SIZE
+    _counter_csv(tmp_path / "cf", [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", copy_bytes / 2048)])
+    _counter_csv(tmp_path / "cw", [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", copy_bytes / 1024)])
+    # two rollout dispatches, each FETCH_SIZE split over two counter instances;
+    # one dispatch of another instantiation (an autotune candidate) is ignored
+    _counter_csv(tmp_path / "f", [(5, ROLLOUT, "FETCH_SIZE", 100.0), (5, ROLLOUT, "FETCH_SIZE", 200.0),
+                                  (6, ROLLOUT, "FETCH_SIZE", 150.0), (6, ROLLOUT, "FETCH_SIZE", 150.0),
+                                  (7, ROLLOUT.replace("16, 8", "64, 8"), "FETCH_SIZE", 9999.0)])
+    _counter_csv(tmp_path / "w", [(5, ROLLOUT, "WRITE_SIZE", 250.0), (6, ROLLOUT, "WRITE_SIZE", 260.0)])
+    out = tmp_path / "traffic.json"
+    r = bench.summarize_traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                                str(tmp_path / "cw"), copy_bytes, WORKLOAD, str(out))
+    assert r["fetch_scale"] == pytest.approx(2.0) and r["write_scale"] == pytest.approx(1.0)
+    assert r["fetch_kib_raw"] == pytest.approx(300.0) and r["write_kib_raw"] == pytest.approx(255.0)
+    assert r["dispatches"] == [2, 2] and r["kernels"] == [ROLLOUT]
+    assert r["bytes_per_launch"] == pytest.approx(300.0 * 1024 * 2 + 255.0 * 1024)
+    # the bench reads the record back only while the kernel source is unchanged
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    os.replace(out, tmp_path / "profiles" / "traffic.json")
+    assert bench.load_traffic("rollout", WORKLOAD) == pytest.approx(r["bytes_per_launch"])
+    assert bench.load_traffic("rollout", "another workload") is None
+    monkeypatch.setattr(bench, "_kernel_digest", lambda text=None: "00000000000000bb")
+    assert bench.load_traffic("rollout", WORKLOAD) is None
+
+
+def test_counter_summary(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "_kernel_digest", lambda text=None: "00000000000000aa")
+    # one dispatch: 4 waves of 1000 cycles each, VALU active 600 (units of 4
+    # cycles), 1200 VALU instructions, of which 60 transcendental
+    _counter_csv(tmp_path / "sq1", [(3, ROLLOUT, "SQ_ACTIVE_INST_VALU", 600.0), (3, ROLLOUT, "SQ_WAVE_CYCLES", 4000.0),
+                                    (3, ROLLOUT, "SQ_WAVES", 4.0), (3, ROLLOUT, "SQ_INSTS_VALU", 1200.0),
+                                    (3, ROLLOUT, "SQ_WAIT_ANY", 2000.0)])
+    _counter_csv(tmp_path / "sq2", [(4, ROLLOUT, "SQ_INSTS_VALU_TRANS_F32", 60.0)])
+    out = tmp_path / "counters.json"
+    r = bench.summarize_counters(str(tmp_path / "sq1"), str(tmp_path / "sq2"), WORKLOAD, str(out))
+    assert r["valu_busy"] == pytest.approx(0.6)
+    assert r["valu_insts_per_wave"] == pytest.approx(300.0)
+    assert r["wait_frac"] == pytest.approx(0.5) and r["trans_share"] == pytest.approx(0.05)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    os.replace(out, tmp_path / "profiles" / "counters.json")
+    assert bench.load_counters("rollout", WORKLOAD) == {"valu_busy": pytest.approx(0.6),
+                                                        "valu_insts_per_wave": pytest.approx(300.0),
+                                                        "wait_frac": pytest.approx(0.5)}
+
+
+def test_committed_records_match_the_kernel_source():
+    """The committed traffic and counter records were taken on the kernel
+    source in the tree (otherwise the bench reports null for them)."""
+    for name in ("traffic.json", "counters.json"):
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        assert rec["rollout"][WORKLOAD]["kernel_source_sha256_16"] == bench._kernel_digest(), name
+
+
+def test_vehicle_workload_flops():
+    """8 FLOPs a pair (P x J pairs), 8 a shape point and, for the vehicle, 84
+    fixed per rollout step (noise 34, saturation 4, dynamics 14, heading 2,
+    barrier state 2, stage cost 16, control cost 6, compensated add 6):
+    6 548 per step and 1.341 GFLOP per launch at K=4096, T=50, J=100."""
+    wl = W.car()
+    p = wl["params"]
+    per_step = bench.rollout_flops_per_step(p, len(wl["obstacles"]), False)
+    assert per_step == 6548
+    assert p["K"] * p["T"] * per_step == 1341030400
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
