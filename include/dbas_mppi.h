@@ -2,7 +2,7 @@
  * dbas_mppi.h -- C ABI of the MI355X (gfx950) DBaS-Log-MPPI library.
  *
  * One call of mppi_step runs one iteration of the sampling-based controller of
- * Yin et al., "DBaS-Log-MPPI: Efficient and Safe Trajectory Optimization via
+ * Wang, Jiang, Tao, Wan and Cheng, "DBaS-Log-MPPI: Efficient and Safe Trajectory Optimization via
  * Barrier States": draw K normal x log-normal perturbation sequences of
  * horizon T (Sec. IV-C), roll the barrier-state-augmented dynamics out for
  * every sample while accumulating the cost-to-go (Sec. IV-A, eq.

@@ -6,7 +6,7 @@
  * smoke check and the CPU-baseline leg of the benchmark do.  It shares no
  * header, helper, table or constant with the GPU implementation.
  *
- * Every function follows a named part of the paper (Yin et al., "DBaS-Log-MPPI:
+ * Every function follows a named part of the paper (Wang, Jiang, Tao, Wan and Cheng, "DBaS-Log-MPPI:
  * Efficient and Safe Trajectory Optimization via Barrier States"):
  *   Sec. III-A  MPPI problem, cost-to-go, min-shifted exponential update
  *   Sec. III-B  discrete barrier states (eq. barrier_state, eq. barrier_update)

@@ -2,17 +2,17 @@
 Philox sampling, barrier-state-augmented rollout, min-shifted exponential
 weighting and weighted-average update) as HIP kernels behind a C ABI.
 
-Importing the package loads nothing; ``controller`` loads libdbasmppi.so on
-first use and raises if it is missing.
+Importing the package loads nothing; the handle classes (Controller, Batch,
+Server, all in ``controller``) load libdbasmppi.so on first use and raise if
+it is missing.
 """
 __all__ = ["Controller", "Batch", "Server", "workloads"]
 
 
 def __getattr__(name):
-    if name in ("Controller", "Batch"):
-        from . import controller
-        return getattr(controller, name)
-    if name == "Server":
-        from . import server
-        return server.Server
+    import importlib
+    if name in ("Controller", "Batch", "Server"):
+        return getattr(importlib.import_module(__name__ + ".controller"), name)
+    if name == "workloads":
+        return importlib.import_module(__name__ + ".workloads")
     raise AttributeError(name)

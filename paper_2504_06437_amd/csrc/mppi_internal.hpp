@@ -242,7 +242,15 @@ inline size_t tile_lds_bytes(int J, int T, int n, int S)
            (tile_keeps_noise(J, T, n, S) ? (size_t)T * S * 8 : 0);
 }
 
-// Kernel launchers (mppi_kernels.hip).
+// Kernel launchers (mppi_kernels.hip).  The rollout kernels of each model
+// live in their own unit (mppi_rollout_<model>.hip).
+using BatchRolloutKernel = void (*)(const DevParams*, const BatchUnit*, int, const BatchIn*, uint32_t*);
+hipError_t launch_rollout_quad6(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rollout_quad5(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_rollout_car(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
+BatchRolloutKernel batch_rollout_kernel_quad6();
+BatchRolloutKernel batch_rollout_kernel_quad5();
+BatchRolloutKernel batch_rollout_kernel_car();
 hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s);
 // One persistent rollout launch per group, in order of decreasing work, each

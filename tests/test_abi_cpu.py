@@ -52,3 +52,16 @@ def test_binding_config_from_workload_params():
     assert c.model == 2 and c.P == 8 and c.shape[0][0] == 2.0 and abs(c.shape[0][1] - 1.5) < 1e-7
     c = make_config(W.base_params("quad5", 64, 5))
     assert abs(c.sigma[0] ** 2 - 0.4) < 1e-6 and abs(c.sigma[1] ** 2 - 0.12) < 1e-6
+
+
+def test_package_lazy_exports_resolve():
+    """Every name the package lists resolves to the class in ``controller``
+    (no library load is needed to resolve them)."""
+    import paper_2504_06437_amd as pkg
+    from paper_2504_06437_amd import controller
+    for name in pkg.__all__:
+        obj = getattr(pkg, name)
+        if name != "workloads":
+            assert obj is getattr(controller, name)
+    with pytest.raises(AttributeError):
+        getattr(pkg, "NoSuchThing")
