@@ -29,14 +29,25 @@ OK, INVALID, NUMERIC = 0, 1, 4
 PMAX = 16
 
 
+GCC_FLAGS = ["-O2", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared"]
+SAMPLING = {"nln": 0, "normal": 1}
+COST_MODE = {"dbas": 0, "indicator": 1}
+
+
+def compile_library(src: str, out: str, include: str | None = None) -> str:
+    """Compile an oracle source file into a shared library (gcc -O2, no
+    fast-math, OpenMP over samples)."""
+    tmp = out + ".tmp"
+    inc = ["-I", include] if include else []
+    subprocess.check_call(["gcc", *GCC_FLAGS, *inc, src, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, no fast-math)."""
+    """Compile liboracle.so."""
     if force or not os.path.exists(LIB_PATH):
-        src = os.path.join(_HERE, "oracle.c")
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra",
-                               "-fPIC", "-shared", src, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB_PATH)
+        compile_library(os.path.join(_HERE, "oracle.c"), LIB_PATH)
     return LIB_PATH
 
 
@@ -54,6 +65,7 @@ class _Cfg(ctypes.Structure):
         ("Q", ctypes.c_double * 6), ("Qf", ctypes.c_double * 6),
         ("P", ctypes.c_int), ("shape", (ctypes.c_double * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("init_zero", ctypes.c_int),
+        ("sampling", ctypes.c_int), ("cost_mode", ctypes.c_int), ("collision_weight", ctypes.c_double),
     ]
 
 
@@ -69,41 +81,84 @@ class _World(ctypes.Structure):
 _lib = None
 
 
+def _load(path: str):
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    cp = ctypes.POINTER(_Cfg)
+    wp = ctypes.POINTER(_World)
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = ctypes.c_int
+    L.orc_threads.restype = ctypes.c_int
+    L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+    L.orc_uniform.argtypes = [ctypes.c_uint32]
+    L.orc_uniform.restype = ctypes.c_double
+    L.orc_noise_words.argtypes = [cp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
+    L.orc_noise.argtypes = [cp, ctypes.c_double, ctypes.c_uint64, dp]
+    L.orc_dynamics.argtypes = [cp, dp, dp, dp]
+    L.orc_shape_points.argtypes = [cp, dp, dp]
+    L.orc_sdf_lookup.argtypes = [wp, ctypes.c_double, ctypes.c_double]
+    L.orc_sdf_lookup.restype = ctypes.c_double
+    L.orc_fused_barrier.argtypes = [cp, wp, dp]
+    L.orc_fused_barrier.restype = ctypes.c_double
+    L.orc_barrier_sensitivity.argtypes = [cp, wp, dp]
+    L.orc_barrier_sensitivity.restype = ctypes.c_double
+    L.orc_collision.argtypes = [cp, wp, dp]
+    L.orc_collision.restype = ctypes.c_int
+    L.orc_rollout_one.argtypes = [cp, wp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+    L.orc_rollout_one.restype = ctypes.c_double
+    L.orc_exploration.argtypes = [cp, wp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
+    L.orc_exploration.restype = ctypes.c_double
+    L.orc_clearance.argtypes = [cp, wp, dp]
+    L.orc_clearance.restype = ctypes.c_double
+    L.orc_margins.argtypes = [cp, wp, dp, dp, dp, dp]
+    L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
+    L.orc_weights.restype = ctypes.c_int
+    L.orc_update.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_shift.argtypes = [cp, dp, dp]
+    L.orc_step.argtypes = [cp, wp, dp, dp, dp, ctypes.c_double, ctypes.c_uint64,
+                           dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.orc_step.restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        cp = ctypes.POINTER(_Cfg)
-        wp = ctypes.POINTER(_World)
-        L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
-        L.orc_uniform.argtypes = [ctypes.c_uint32]
-        L.orc_uniform.restype = ctypes.c_double
-        L.orc_noise_words.argtypes = [cp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)]
-        L.orc_noise.argtypes = [cp, ctypes.c_double, ctypes.c_uint64, dp]
-        L.orc_dynamics.argtypes = [cp, dp, dp, dp]
-        L.orc_shape_points.argtypes = [cp, dp, dp]
-        L.orc_sdf_lookup.argtypes = [wp, ctypes.c_double, ctypes.c_double]
-        L.orc_sdf_lookup.restype = ctypes.c_double
-        L.orc_fused_barrier.argtypes = [cp, wp, dp]
-        L.orc_fused_barrier.restype = ctypes.c_double
-        L.orc_rollout_one.argtypes = [cp, wp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
-        L.orc_rollout_one.restype = ctypes.c_double
-        L.orc_exploration.argtypes = [cp, wp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_exploration.restype = ctypes.c_double
-        L.orc_clearance.argtypes = [cp, wp, dp]
-        L.orc_clearance.restype = ctypes.c_double
-        L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
-        L.orc_weights.restype = ctypes.c_int
-        L.orc_update.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_shift.argtypes = [cp, dp, dp]
-        L.orc_step.argtypes = [cp, wp, dp, dp, dp, ctypes.c_double, ctypes.c_uint64,
-                               dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
-        L.orc_step.restype = ctypes.c_int
-        _lib = L
+        _lib = _load(LIB_PATH)
+        _lib.orc_set_threads(int(os.environ.get("ORACLE_THREADS", "1")))
     return _lib
+
+
+class use_library:
+    """Context manager: run the wrappers below on another build of the oracle
+    (a library compiled by ``compile_library``), then restore the usual one.
+    The tests use it to check that planted mistakes are caught."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _load(self.path)
+        _lib.orc_set_threads(self.saved.orc_threads())
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's per-sample loops (results do not depend on it)."""
+    return lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return lib().orc_threads()
 
 
 def _dp(a):
@@ -148,6 +203,9 @@ def make_cfg(params: dict) -> _Cfg:
         c.shape[i][1] = shape[i, 1]
     c.seed = int(params["seed"]) & 0xFFFFFFFFFFFFFFFF
     c.init_zero = 1 if params.get("init_mode", "repeat") == "zero" else 0
+    c.sampling = SAMPLING[params.get("sampling", "nln")]
+    c.cost_mode = COST_MODE[params.get("cost_mode", "dbas")]
+    c.collision_weight = float(params.get("collision_weight", 1000.0))
     return c
 
 
@@ -263,6 +321,25 @@ def exploration(params: dict, world: World, x0, Ustar, beta_d: float, mu: float)
     se = lib().orc_exploration(ctypes.byref(cfg), ctypes.byref(world.s), _dp(_f64(x0)), _dp(_f64(Ustar)),
                                float(beta_d), float(mu), ctypes.byref(cb))
     return se, cb.value
+
+
+def barrier_sensitivity(params: dict, world: World, x) -> float:
+    cfg = make_cfg(params)
+    return lib().orc_barrier_sensitivity(ctypes.byref(cfg), ctypes.byref(world.s), _dp(_f64(x)))
+
+
+def collision(params: dict, world: World, x) -> int:
+    cfg = make_cfg(params)
+    return lib().orc_collision(ctypes.byref(cfg), ctypes.byref(world.s), _dp(_f64(x)))
+
+
+def margins(params: dict, world: World, x0, U, du) -> np.ndarray:
+    """min over t = 1..T of |clearance(x_t)| for every sample's rollout."""
+    cfg = make_cfg(params)
+    du = _f64(du)
+    out = np.zeros(cfg.K)
+    lib().orc_margins(ctypes.byref(cfg), ctypes.byref(world.s), _dp(_f64(x0)), _dp(_f64(U)), _dp(du), _dp(out))
+    return out
 
 
 def clearance(params: dict, world: World, x) -> float:

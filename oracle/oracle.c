@@ -13,6 +13,24 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 1;
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    g_threads = n < 1 ? 1 : n;
+#else
+    (void)n;
+    g_threads = 1;
+#endif
+    return g_threads;
+}
+
+int orc_threads(void) { return g_threads; }
 
 int orc_state_dim(int model)
 {
@@ -75,27 +93,37 @@ void orc_noise_words(const orc_cfg* cfg, uint64_t counter, uint32_t* words)
  * the normal part is N(0, S_e Sigma_u), i.e. standard deviation
  * sqrt(S_e) sigma_c; the log-normal factor is exp(mu_ln + sigma_ln z) with an
  * independent standard normal z.  Standard normals come from the Box-Muller
- * transform of two uniforms each. */
-void orc_noise(const orc_cfg* cfg, double S_e, uint64_t counter, double* du)
+ * transform of two uniforms each.  Vanilla MPPI's sampling (ORC_SAMPLE_NORMAL)
+ * is the normal part alone. */
+static void noise_sample(const orc_cfg* cfg, double S_e, uint64_t counter, int k, double* du_k)
 {
     const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 0; k < cfg->K; ++k) {
-        for (int t = 0; t < cfg->T; ++t) {
-            uint32_t r[4];
-            noise_block(cfg, counter, k, t, r);
-            double u0 = orc_uniform(r[0]), u1 = orc_uniform(r[1]);
-            double u2 = orc_uniform(r[2]), u3 = orc_uniform(r[3]);
-            double rad_n = sqrt(-2.0 * log(u0));
-            double rad_z = sqrt(-2.0 * log(u2));
-            double n[2] = {rad_n * cos(two_pi * u1), rad_n * sin(two_pi * u1)};
-            double z[2] = {rad_z * cos(two_pi * u3), rad_z * sin(two_pi * u3)};
-            for (int c = 0; c < ORC_M; ++c) {
-                double normal_part = sqrt(S_e) * cfg->sigma[c] * n[c];
+    for (int t = 0; t < cfg->T; ++t) {
+        uint32_t r[4];
+        noise_block(cfg, counter, k, t, r);
+        double u0 = orc_uniform(r[0]), u1 = orc_uniform(r[1]);
+        double u2 = orc_uniform(r[2]), u3 = orc_uniform(r[3]);
+        double rad_n = sqrt(-2.0 * log(u0));
+        double rad_z = sqrt(-2.0 * log(u2));
+        double n[2] = {rad_n * cos(two_pi * u1), rad_n * sin(two_pi * u1)};
+        double z[2] = {rad_z * cos(two_pi * u3), rad_z * sin(two_pi * u3)};
+        for (int c = 0; c < ORC_M; ++c) {
+            double normal_part = sqrt(S_e) * cfg->sigma[c] * n[c];
+            if (cfg->sampling == ORC_SAMPLE_NORMAL) {
+                du_k[t * ORC_M + c] = normal_part;
+            } else {
                 double lognormal_part = exp(cfg->mu_ln + cfg->sigma_ln * z[c]);
-                du[((size_t)k * cfg->T + t) * ORC_M + c] = normal_part * lognormal_part;
+                du_k[t * ORC_M + c] = normal_part * lognormal_part;
             }
         }
     }
+}
+
+void orc_noise(const orc_cfg* cfg, double S_e, uint64_t counter, double* du)
+{
+    int k;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (k = 0; k < cfg->K; ++k) noise_sample(cfg, S_e, counter, k, du + (size_t)k * cfg->T * ORC_M);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -236,11 +264,35 @@ double orc_clearance(const orc_cfg* cfg, const orc_world* w, const double* x)
     return m;
 }
 
+/* Partial derivatives of the bilinear costmap reading at (px, py), from the
+ * cell the lookup uses (zero along an axis where the point is clamped to the
+ * edge). */
+static void sdf_partials(const orc_world* w, double px, double py, double* dx_out, double* dy_out)
+{
+    double gx = (px - w->map_x0) / w->map_res - 0.5;
+    double gy = (py - w->map_y0) / w->map_res - 0.5;
+    int clamped_x = gx < 0.0 || gx > (double)(w->map_w - 1);
+    int clamped_y = gy < 0.0 || gy > (double)(w->map_h - 1);
+    gx = clampd(gx, 0.0, (double)(w->map_w - 1));
+    gy = clampd(gy, 0.0, (double)(w->map_h - 1));
+    int i0 = (int)floor(gx), j0 = (int)floor(gy);
+    if (i0 > w->map_w - 2) i0 = w->map_w - 2;
+    if (j0 > w->map_h - 2) j0 = w->map_h - 2;
+    double fx = gx - i0, fy = gy - j0;
+    const double* s = w->sdf;
+    double s00 = s[(size_t)j0 * w->map_w + i0], s01 = s[(size_t)j0 * w->map_w + i0 + 1];
+    double s10 = s[(size_t)(j0 + 1) * w->map_w + i0], s11 = s[(size_t)(j0 + 1) * w->map_w + i0 + 1];
+    *dx_out = clamped_x ? 0.0 : ((1.0 - fy) * (s01 - s00) + fy * (s11 - s10)) / w->map_res;
+    *dy_out = clamped_y ? 0.0 : ((1.0 - fx) * (s10 - s00) + fx * (s11 - s01)) / w->map_res;
+}
+
 /* Sensitivity of the fused barrier at state x to a displacement of every
- * shape point by at most 1 (metre) per coordinate: the sum over unclamped
- * terms of |dB/dp| = sqrt(2) |dh/dp| / h^2, with |dh/dp| = 2 |p - c| for a
- * circle and <= 1 for the costmap (a signed distance has unit gradient).
- * A diagnostic for the comparison tolerance, not part of the controller. */
+ * shape point by at most 1 (metre) in each coordinate: to first order the
+ * largest change is the sum over the unclamped terms of
+ * |dB/dp_x| + |dB/dp_y| = (|dh/dp_x| + |dh/dp_y|) / h^2, with
+ * dh/dp = 2 (p - c) for a circle and the bilinear reading's partials for the
+ * costmap.  A diagnostic for the comparison tolerance, not part of the
+ * controller. */
 double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x)
 {
     double pts[2 * ORC_PMAX];
@@ -252,19 +304,33 @@ double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const dou
             double dy = pts[2 * i + 1] - w->obs[3 * j + 1];
             double r = w->obs[3 * j + 2];
             double h = dx * dx + dy * dy - r * r;
-            if (h > cfg->h_eps) s += sqrt(2.0) * 2.0 * sqrt(dx * dx + dy * dy) / (h * h);
+            if (h > cfg->h_eps) s += 2.0 * (fabs(dx) + fabs(dy)) / (h * h);
         }
         if (w->sdf != NULL && w->map_w > 0) {
             double h = orc_sdf_lookup(w, pts[2 * i], pts[2 * i + 1]);
-            if (h > cfg->h_eps) s += sqrt(2.0) / (h * h);
+            if (h > cfg->h_eps) {
+                double gx, gy;
+                sdf_partials(w, pts[2 * i], pts[2 * i + 1], &gx, &gy);
+                s += (fabs(gx) + fabs(gy)) / (h * h);
+            }
         }
     }
     return s;
 }
 
+/* Sec. IV-A: the constraint set is h >= 0 for every shape point and every
+ * constraint; Vanilla MPPI's indicator marks a state that leaves it. */
+int orc_collision(const orc_cfg* cfg, const orc_world* w, const double* x)
+{
+    return orc_clearance(cfg, w, x) < 0.0 ? 1 : 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rollout of one sample (Algorithm 1, the inner loop; eq. MPPI_BaS,         */
 /* eq. barrier_update, eq. cost-to-go_bas).                                  */
+/* With the indicator cost (the comparison controllers of Sec. V) there is   */
+/* no barrier state: R_B beta is replaced by w_I 1[x_t violates a            */
+/* constraint].                                                              */
 /*   beta_0 = fused B(h(x0))                                                 */
 /*   for t = 0..T-1:  v = U_t + du_t;  x <- f(x, v)                           */
 /*       beta <- fused B(h(x)) - gamma_B (beta_d - beta)                     */
@@ -284,7 +350,8 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
     double x[ORC_NMAX], xn[ORC_NMAX];
     for (int a = 0; a < n; ++a) x[a] = x0[a];
     if (X) for (int a = 0; a < n; ++a) X[a] = x[a];
-    double beta = orc_fused_barrier(cfg, w, x);
+    const int dbas = cfg->cost_mode != ORC_COST_INDICATOR;
+    double beta = dbas ? orc_fused_barrier(cfg, w, x) : 0.0;
     if (beta_out) beta_out[0] = beta;
     double S = 0.0;
     for (int t = 0; t < cfg->T; ++t) {
@@ -292,8 +359,14 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
         for (int c = 0; c < ORC_M; ++c) v[c] = U[t * ORC_M + c] + du_k[t * ORC_M + c];
         orc_dynamics(cfg, x, v, xn);
         for (int a = 0; a < n; ++a) x[a] = xn[a];
-        double b = orc_fused_barrier(cfg, w, x);
-        beta = b - cfg->gamma_b * (beta_d - beta);
+        double collision_term;
+        if (dbas) {
+            double b = orc_fused_barrier(cfg, w, x);
+            beta = b - cfg->gamma_b * (beta_d - beta);
+            collision_term = cfg->r_b * beta;
+        } else {
+            collision_term = cfg->collision_weight * (double)orc_collision(cfg, w, x);
+        }
         const double* ref = x_ref + (size_t)(t + 1) * n;
         double q = 0.0;
         for (int a = 0; a < n; ++a) q += cfg->Q[a] * (x[a] - ref[a]) * (x[a] - ref[a]);
@@ -301,7 +374,7 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
         for (int c = 0; c < ORC_M; ++c)
             if (cfg->sigma[c] > 0.0)
                 ctrl += U[t * ORC_M + c] * v[c] / (S_e * cfg->sigma[c] * cfg->sigma[c]);
-        S += q + cfg->gamma_u * ctrl + cfg->r_b * beta;
+        S += q + cfg->gamma_u * ctrl + collision_term;
         if (X) for (int a = 0; a < n; ++a) X[(size_t)(t + 1) * n + a] = x[a];
         if (beta_out) beta_out[t + 1] = beta;
         if (min_h) {
@@ -310,7 +383,7 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
         }
         /* a change db_t of the fused barrier reaches the cost through
          * beta_t, beta_t+1, ... with weights summing to at most 1/(1-gamma_B) */
-        if (sens) *sens += cfg->r_b / (1.0 - cfg->gamma_b) * orc_barrier_sensitivity(cfg, w, x);
+        if (sens && dbas) *sens += cfg->r_b / (1.0 - cfg->gamma_b) * orc_barrier_sensitivity(cfg, w, x);
     }
     const double* refT = x_ref + (size_t)cfg->T * n;
     double phi = 0.0;
@@ -341,6 +414,29 @@ double orc_exploration(const orc_cfg* cfg, const orc_world* w, const double* x0,
     }
     if (C_B_out) *C_B_out = C_B;
     return mu * log(exp(1.0) + (C_B > 0.0 ? C_B : 0.0));
+}
+
+void orc_margins(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* U, const double* du,
+                 double* margin)
+{
+    const int n = orc_state_dim(cfg->model);
+    int k;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (k = 0; k < cfg->K; ++k) {
+        double x[ORC_NMAX], xn[ORC_NMAX];
+        for (int a = 0; a < n; ++a) x[a] = x0[a];
+        double m = INFINITY;
+        for (int t = 0; t < cfg->T; ++t) {
+            double v[ORC_M];
+            for (int c = 0; c < ORC_M; ++c)
+                v[c] = U[t * ORC_M + c] + du[((size_t)k * cfg->T + t) * ORC_M + c];
+            orc_dynamics(cfg, x, v, xn);
+            for (int a = 0; a < n; ++a) x[a] = xn[a];
+            double h = fabs(orc_clearance(cfg, w, x));
+            if (h < m) m = h;
+        }
+        margin[k] = m;
+    }
 }
 
 /* eq. control_update: rho = min_k S_k; e_k = exp(-(S_k - rho)/lambda);
@@ -407,7 +503,9 @@ int orc_step(const orc_cfg* cfg, const orc_world* w, const double* x0, const dou
     if (beta0_out) *beta0_out = orc_fused_barrier(cfg, w, x0);
 
     orc_noise(cfg, S_e, counter, du);
-    for (int k = 0; k < K; ++k)
+    int k;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(g_threads)
+    for (k = 0; k < K; ++k)
         S[k] = orc_rollout_one(cfg, w, x0, U, du + (size_t)k * T * ORC_M, x_ref, S_e, beta_d, NULL, NULL,
                                clear ? clear + k : NULL, sens ? sens + k : NULL);
     int status = orc_weights(S, K, cfg->lambda, wt, rho, eta);

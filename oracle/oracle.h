@@ -16,6 +16,10 @@
  *   Algorithm 1 the loop order (sampling, rollout, cost, weighting, shift)
  *   Sec. V-A/B  planar quadrotor and Ackermann vehicle (eq. veh_dyn), shape
  *               points and the circular-obstacle function h
+ *   Sec. IV-A, Sec. V and the mission table: the comparison controllers --
+ *               Vanilla MPPI (normal sampling, weighted collision indicator)
+ *               and Log-MPPI (normal x log-normal sampling, the same
+ *               indicator) -- as modes of the same iteration
  * Where the paper is silent the reading used is stated at the function.
  *
  * Parity pins: every function here is pinned by the CPU tests against closed
@@ -35,6 +39,13 @@ extern "C" {
 
 enum { ORC_QUAD6 = 0, ORC_QUAD5 = 1, ORC_CAR = 2 };
 enum { ORC_OK = 0, ORC_INVALID = 1, ORC_NUMERIC = 4 };
+/* Sampling law of the perturbations: the normal x log-normal mixture of
+ * Sec. IV-C, or the plain normal law of Vanilla MPPI. */
+enum { ORC_SAMPLE_NLN = 0, ORC_SAMPLE_NORMAL = 1 };
+/* Collision term of the running cost: the barrier state of Sec. IV-A, or the
+ * weighted indicator of a constraint violation that Sec. IV-A describes for
+ * Vanilla MPPI (and that the Log-MPPI baseline shares). */
+enum { ORC_COST_DBAS = 0, ORC_COST_INDICATOR = 1 };
 
 #define ORC_M 2          /* every model here has two inputs */
 #define ORC_NMAX 6
@@ -58,6 +69,9 @@ typedef struct {
     double shape[ORC_PMAX][2]; /* body-frame offsets (along heading, normal) */
     uint64_t seed;
     int init_zero;             /* 0: new last control repeats the old last, 1: zero */
+    int sampling;              /* ORC_SAMPLE_NLN or ORC_SAMPLE_NORMAL */
+    int cost_mode;             /* ORC_COST_DBAS or ORC_COST_INDICATOR */
+    double collision_weight;   /* weight of the indicator term (ORC_COST_INDICATOR) */
 } orc_cfg;
 
 typedef struct {
@@ -70,6 +84,13 @@ typedef struct {
 
 int orc_state_dim(int model);
 
+/* Worker threads of the per-sample loops (noise, rollouts, margins); 1 runs
+ * them serially.  Every sample is computed by the same code whichever thread
+ * runs it, and every cross-sample sum (weights, update) stays serial, so the
+ * results do not depend on the count.  Returns the count in use. */
+int orc_set_threads(int n);
+int orc_threads(void);
+
 /* Philox4x32-10 (Salmon et al., SC'11): counter ctr, key -> 4 words. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -79,7 +100,8 @@ double orc_uniform(uint32_t r);
 /* Raw Philox words for every (k, t): words[(k*T + t)*4 + i]. */
 void orc_noise_words(const orc_cfg* cfg, uint64_t counter, uint32_t* words);
 
-/* NLN noise du[(k*T + t)*2 + c] for step counter `counter` and exploration S_e. */
+/* Noise du[(k*T + t)*2 + c] for step counter `counter` and exploration S_e:
+ * the NLN mixture, or (ORC_SAMPLE_NORMAL) its normal part alone. */
 void orc_noise(const orc_cfg* cfg, double S_e, uint64_t counter, double* du);
 
 /* One explicit-Euler step with the inputs saturated inside f. */
@@ -97,14 +119,20 @@ double orc_fused_barrier(const orc_cfg* cfg, const orc_world* w, const double* x
 /* Smallest h over all shape points and constraints at state x (diagnostic). */
 double orc_clearance(const orc_cfg* cfg, const orc_world* w, const double* x);
 
-/* Sum over unclamped barrier terms at x of |dB/dp| for a unit displacement of
- * every shape point (diagnostic). */
+/* Largest first-order change of the fused barrier at x when every shape
+ * point moves by at most 1 (metre) in each coordinate: the sum over the
+ * unclamped terms of |dB/dp_x| + |dB/dp_y| (diagnostic). */
 double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x);
 
+/* Collision indicator of state x: 1 when some shape point violates a
+ * constraint (h < 0 for a circle or the costmap), else 0. */
+int orc_collision(const orc_cfg* cfg, const orc_world* w, const double* x);
+
 /* Rollout of one sample.  Returns its cost S.  Optional outputs:
- * X[(T+1)*n] states, beta[T+1] barrier states (beta[0] = beta_0), min_h the
- * smallest clearance over steps 1..T, sens the bound on |dS| per metre of
- * shape-point displacement through the barrier (diagnostics for comparison
+ * X[(T+1)*n] states, beta[T+1] barrier states (beta[0] = beta_0; all zero
+ * with the indicator cost), min_h the smallest clearance over steps 1..T,
+ * sens the bound on |dS| per metre of shape-point displacement through the
+ * barrier (0 with the indicator cost) (diagnostics for comparison
  * tolerances). */
 double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
                        const double* U, const double* du_k, const double* x_ref,
@@ -117,6 +145,12 @@ double orc_rollout_one(const orc_cfg* cfg, const orc_world* w, const double* x0,
  * negative C_B (possible when beta_d is large) enters the logarithm as 0. */
 double orc_exploration(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* Ustar,
                        double beta_d, double mu, double* C_B);
+
+/* Indicator margins of every sample's rollout (diagnostic for the indicator
+ * cost): margin[k] = min over t = 1..T of |clearance(x_t)|, how far the
+ * sample's closest decision of the indicator is from flipping. */
+void orc_margins(const orc_cfg* cfg, const orc_world* w, const double* x0, const double* U, const double* du,
+                 double* margin);
 
 /* Min-shifted exponential weights.  Returns ORC_OK or ORC_NUMERIC. */
 int orc_weights(const double* S, int K, double lambda, double* w, double* rho, double* eta);

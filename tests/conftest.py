@@ -32,3 +32,12 @@ def f32_params(params: dict) -> dict:
             return [r(x) for x in v]
         return v
     return {k: r(v) for k, v in params.items()}
+
+
+def pytest_sessionstart(session):
+    # the oracle's per-sample loops run on the host's cores (the results do
+    # not depend on the thread count)
+    import oracle
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+    oracle.set_threads(min(os.cpu_count() or 1, 16))

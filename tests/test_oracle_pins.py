@@ -560,3 +560,73 @@ def test_savitzky_golay_reproduces_polynomials_up_to_its_order(orc):
     y = rng.standard_normal((12, 2))
     np.testing.assert_array_equal(orc.sgf(y, 0, 0), y)
     np.testing.assert_allclose(orc.sgf(y, 2, 4), y, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The comparison controllers of Sec. V (Vanilla MPPI: normal sampling; both
+# baselines: the weighted collision indicator of Sec. IV-A)
+# ---------------------------------------------------------------------------
+
+def test_normal_sampling_is_the_mixture_without_its_lognormal_factor(orc):
+    """Vanilla sampling draws the normal part alone: bit for bit the mixture
+    with mu_ln = sigma_ln = 0 (whose log-normal factor is exp(0) = 1), and a
+    standard normal law after scaling."""
+    p = _params(K=20000, T=4, sigma=[0.7, 1.9], mu_ln=0.4, sigma_ln=0.6)
+    S_e = 2.2
+    du_n = orc.noise(dict(p, sampling="normal"), counter=31, S_e=S_e)
+    du_0 = orc.noise(dict(p, mu_ln=0.0, sigma_ln=0.0), counter=31, S_e=S_e)
+    np.testing.assert_array_equal(du_n, du_0)
+    flat = du_n.reshape(-1, 2)
+    for c, sig in enumerate(p["sigma"]):
+        assert stats.kstest(flat[:, c] / (math.sqrt(S_e) * sig), "norm").pvalue > 1e-3
+    assert not np.array_equal(du_n, orc.noise(p, counter=31, S_e=S_e))
+
+
+def test_indicator_counts_the_steps_inside_an_obstacle(orc):
+    """A one-point vehicle driving straight at 10 m/s (dt 0.1, no noise, no
+    input): x_t = t metres.  An obstacle centred at x = 5 with r = 1.5 holds
+    steps 4, 5 and 6, so the indicator cost exceeds the collision-free cost by
+    exactly 3 w_I; the barrier-state cost of the same rollout with R_B = 0 is
+    the collision-free cost."""
+    p = W.base_params("car", 1, 10)
+    p.update(dt=0.1, shape=[[0.0, 0.0]], sigma=[0.0, 0.0], Q=[0.0] * 4, Qf=[0.0] * 4, collision_weight=77.0)
+    world = orc.World(np.array([[5.0, 0.0, 1.5], [40.0, 40.0, 1.0]]))
+    x0 = np.array([0.0, 0.0, 0.0, 10.0])
+    U = np.zeros((10, 2))
+    du = np.zeros((10, 2))
+    ref = np.zeros((11, 4))
+    S_ind, X, beta, mh, sens = orc.rollout_one(dict(p, cost_mode="indicator"), world, x0, U, du, ref, with_clearance=True)
+    S_free = orc.rollout_one(dict(p, r_b=0.0), world, x0, U, du, ref)[0]
+    np.testing.assert_allclose(X[:, 0], np.arange(11.0) * 1.0, rtol=0, atol=1e-12)
+    assert S_free == 0.0
+    assert S_ind == 3 * 77.0
+    assert np.all(beta == 0.0) and sens == 0.0
+    assert mh == -2.25
+
+
+def test_indicator_treats_the_boundary_as_safe(orc):
+    """The constraint set is h >= 0: a shape point exactly on the circle is
+    not a collision, one just inside is."""
+    p = W.base_params("car", 1, 1)
+    p["shape"] = [[0.0, 0.0]]
+    world = orc.World(np.array([[5.0, 0.0, 1.0]]))
+    assert orc.clearance(p, world, [4.0, 0.0, 0.0, 0.0]) == 0.0
+    assert orc.collision(p, world, [4.0, 0.0, 0.0, 0.0]) == 0
+    assert orc.collision(p, world, [4.0 + 2.0 ** -20, 0.0, 0.0, 0.0]) == 1
+    sdf = np.full((4, 4), 1.0)
+    sdf[1, 1] = -0.5
+    world = orc.World(np.zeros((0, 3)), sdf, (0.0, 0.0), 1.0)
+    assert orc.collision(p, world, [1.5, 1.5, 0.0, 0.0]) == 1
+    assert orc.collision(p, world, [3.5, 3.5, 0.0, 0.0]) == 0
+
+
+def test_indicator_margins_measure_the_closest_decision(orc):
+    """The margin of a sample is min over steps 1..T of |clearance|: on the
+    straight drive above it is the smallest |(t - 5)^2 - 2.25| over
+    t = 1..10, which is 1.25 (at t = 4 and 6)."""
+    p = W.base_params("car", 1, 10)
+    p.update(dt=0.1, shape=[[0.0, 0.0]], sigma=[0.0, 0.0], cost_mode="indicator")
+    world = orc.World(np.array([[5.0, 0.0, 1.5]]))
+    m = orc.margins(p, world, [0.0, 0.0, 0.0, 10.0], np.zeros((10, 2)), np.zeros((1, 10, 2)))
+    ts = np.arange(1, 11, dtype=np.float64)
+    assert abs(m[0] - np.min(np.abs((ts - 5.0) ** 2 - 2.25))) <= 1e-12
