@@ -160,7 +160,7 @@ typedef struct mppi_step_info {
     float S_e;                     /* exploration rate the next iteration samples with */
     float cost_b;                  /* C_B of the last U* (adaptive_explore only, else 0) */
     int32_t barrier_form;          /* 0: the general form; 1: the layout form of Sec. V's bodies (see shape); 2: the quadrotor's mirrored-axis form */
-    int32_t reserved;
+    int32_t noise_kept;            /* 1: each rollout tile keeps its noise in LDS for the update sums; 0: it draws it again */
 } mppi_step_info;
 
 typedef struct mppi_ctrl mppi_t;

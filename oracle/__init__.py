@@ -66,6 +66,7 @@ class _Cfg(ctypes.Structure):
         ("P", ctypes.c_int), ("shape", (ctypes.c_double * 2) * PMAX),
         ("seed", ctypes.c_uint64), ("init_zero", ctypes.c_int),
         ("sampling", ctypes.c_int), ("cost_mode", ctypes.c_int), ("collision_weight", ctypes.c_double),
+        ("sens_reach", ctypes.c_double),
     ]
 
 
@@ -206,6 +207,7 @@ def make_cfg(params: dict) -> _Cfg:
     c.sampling = SAMPLING[params.get("sampling", "nln")]
     c.cost_mode = COST_MODE[params.get("cost_mode", "dbas")]
     c.collision_weight = float(params.get("collision_weight", 1000.0))
+    c.sens_reach = float(params.get("sens_reach", 0.0))
     return c
 
 

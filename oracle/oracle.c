@@ -286,33 +286,45 @@ static void sdf_partials(const orc_world* w, double px, double py, double* dx_ou
     *dy_out = clamped_y ? 0.0 : ((1.0 - fx) * (s10 - s00) + fx * (s11 - s01)) / w->map_res;
 }
 
-/* Sensitivity of the fused barrier at state x to a displacement of every
- * shape point by at most 1 (metre) in each coordinate: to first order the
- * largest change is the sum over the unclamped terms of
- * |dB/dp_x| + |dB/dp_y| = (|dh/dp_x| + |dh/dp_y|) / h^2, with
- * dh/dp = 2 (p - c) for a circle and the bilinear reading's partials for the
- * costmap.  A diagnostic for the comparison tolerance, not part of the
- * controller. */
+/* Steepest slope of B(h) = 1/max(h, h_eps) over [h - d, h + d]: 1/(h - d)^2
+ * at the near end when the interval stays above h_eps, 1/h_eps^2 when it
+ * reaches the cap from above, 0 when it lies below the cap (B is flat there). */
+static double barrier_slope(const orc_cfg* cfg, double h, double d)
+{
+    if (h + d <= cfg->h_eps) return 0.0;
+    double lo = h - d > cfg->h_eps ? h - d : cfg->h_eps;
+    return 1.0 / (lo * lo);
+}
+
+/* Sensitivity of the fused barrier at state x: a bound on its change per
+ * metre when every shape point moves by at most r = sens_reach in each
+ * coordinate.  A term's h then moves by at most d = r (|dh/dp_x| +
+ * |dh/dp_y|), with dh/dp = 2 (p - c) for a circle and the bilinear reading's
+ * partials for the costmap, and its B by at most d times the steepest slope
+ * of B within [h - d, h + d].  With r = 0 the sum is the largest first-order
+ * change, over the unclamped terms of |dB/dp_x| + |dB/dp_y|.  A diagnostic
+ * for the comparison tolerance, not part of the controller. */
 double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x)
 {
     double pts[2 * ORC_PMAX];
     orc_shape_points(cfg, x, pts);
+    const double r = cfg->sens_reach;
     double s = 0.0;
     for (int i = 0; i < cfg->P; ++i) {
         for (int j = 0; j < w->J; ++j) {
             double dx = pts[2 * i] - w->obs[3 * j];
             double dy = pts[2 * i + 1] - w->obs[3 * j + 1];
-            double r = w->obs[3 * j + 2];
-            double h = dx * dx + dy * dy - r * r;
-            if (h > cfg->h_eps) s += 2.0 * (fabs(dx) + fabs(dy)) / (h * h);
+            double rad = w->obs[3 * j + 2];
+            double h = dx * dx + dy * dy - rad * rad;
+            double g = 2.0 * (fabs(dx) + fabs(dy));
+            s += g * barrier_slope(cfg, h, r * g);
         }
         if (w->sdf != NULL && w->map_w > 0) {
             double h = orc_sdf_lookup(w, pts[2 * i], pts[2 * i + 1]);
-            if (h > cfg->h_eps) {
-                double gx, gy;
-                sdf_partials(w, pts[2 * i], pts[2 * i + 1], &gx, &gy);
-                s += (fabs(gx) + fabs(gy)) / (h * h);
-            }
+            double gx, gy;
+            sdf_partials(w, pts[2 * i], pts[2 * i + 1], &gx, &gy);
+            double g = fabs(gx) + fabs(gy);
+            s += g * barrier_slope(cfg, h, r * g);
         }
     }
     return s;

@@ -72,6 +72,7 @@ typedef struct {
     int sampling;              /* ORC_SAMPLE_NLN or ORC_SAMPLE_NORMAL */
     int cost_mode;             /* ORC_COST_DBAS or ORC_COST_INDICATOR */
     double collision_weight;   /* weight of the indicator term (ORC_COST_INDICATOR) */
+    double sens_reach;         /* move per coordinate the barrier sensitivity covers (diagnostic; 0: first order) */
 } orc_cfg;
 
 typedef struct {
@@ -119,9 +120,11 @@ double orc_fused_barrier(const orc_cfg* cfg, const orc_world* w, const double* x
 /* Smallest h over all shape points and constraints at state x (diagnostic). */
 double orc_clearance(const orc_cfg* cfg, const orc_world* w, const double* x);
 
-/* Largest first-order change of the fused barrier at x when every shape
- * point moves by at most 1 (metre) in each coordinate: the sum over the
- * unclamped terms of |dB/dp_x| + |dB/dp_y| (diagnostic). */
+/* Bound on the change of the fused barrier at x, per metre, when every shape
+ * point moves by at most r = sens_reach in each coordinate (diagnostic): the
+ * sum over the terms of (|dh/dp_x| + |dh/dp_y|) times the steepest slope of
+ * B = 1/max(h, h_eps) within the reach of h.  With r = 0 this is the largest
+ * first-order change, sum over the unclamped terms of |dB/dp_x| + |dB/dp_y|. */
 double orc_barrier_sensitivity(const orc_cfg* cfg, const orc_world* w, const double* x);
 
 /* Collision indicator of state x: 1 when some shape point violates a

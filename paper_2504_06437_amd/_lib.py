@@ -71,7 +71,7 @@ class StepInfo(ctypes.Structure):
                 ("rho", ctypes.c_double), ("eta", ctypes.c_double), ("beta0", ctypes.c_float),
                 ("beta_d", ctypes.c_float), ("tile_samples", ctypes.c_int32), ("tiles", ctypes.c_int32),
                 ("S_e", ctypes.c_float), ("cost_b", ctypes.c_float), ("barrier_form", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("noise_kept", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

@@ -816,7 +816,7 @@ extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
     info->S_e = st.S_e;
     info->cost_b = st.cost_b;
     info->barrier_form = h->p.shape_kind;
-    info->reserved = 0;
+    info->noise_kept = tile_keeps_noise(h->p.J, h->cfg.T, h->p.n, h->p.spt) ? 1 : 0;
     return MPPI_OK;
 }
 

@@ -148,9 +148,18 @@ def clearance(p, world, x):
 
 
 def sensitivity(p, world, x):
-    """Worst first-order change of the fused barrier for shape-point moves of
-    at most 1 per coordinate: sum of |grad h|_1 / h^2 over unclamped terms."""
-    return sum((abs(dx) + abs(dy)) / (h * h) for h, dx, dy in constraint_values(p, world, x) if h > p["h_eps"])
+    """Bound on the change of the fused barrier per metre of shape-point move
+    (at most `sens_reach` per coordinate): each term's |grad h|_1 times the
+    largest |dB/dh| of B(h) = 1/max(h, h_eps) for h within |grad h|_1 reach
+    of its value (first order, over the unclamped terms, at reach 0)."""
+    reach, eps = p.get("sens_reach", 0.0), p["h_eps"]
+    total = 0.0
+    for h, dx, dy in constraint_values(p, world, x):
+        g = abs(dx) + abs(dy)
+        lowest = h - reach * g
+        if h + reach * g > eps:
+            total += g / max(lowest, eps) ** 2
+    return total
 
 
 # --- one iteration ---------------------------------------------------------------

@@ -20,9 +20,19 @@ def orc():
     return oracle
 
 
+# Position-error budget of the FP32 rollout (metres per coordinate of a shape
+# point): positions of <= 10 m in the iteration's local frame have an ulp of
+# ~1e-6 m, and <= 100 Euler steps accumulate ~1e-5 m.  The oracle's barrier
+# sensitivity is taken over moves of this reach, and the cost tolerance adds
+# reach x sensitivity to the relative bound.
+SENS_REACH = 1e-5
+
+
 def f32_params(params: dict) -> dict:
     """The parameter dict with every real rounded to binary32, i.e. exactly
-    the values the GPU library receives, so the oracle sees the same inputs."""
+    the values the GPU library receives, so the oracle sees the same inputs;
+    plus the reach of the oracle's barrier sensitivity (an oracle-only
+    diagnostic the library never sees)."""
     import numpy as np
 
     def r(v):
@@ -31,7 +41,9 @@ def f32_params(params: dict) -> dict:
         if isinstance(v, (list, tuple)):
             return [r(x) for x in v]
         return v
-    return {k: r(v) for k, v in params.items()}
+    out = {k: r(v) for k, v in params.items()}
+    out["sens_reach"] = SENS_REACH
+    return out
 
 
 def pytest_sessionstart(session):

@@ -111,3 +111,51 @@ def test_batch_groups_by_model(models):
     batch.close()
     for c in alone + mixed:
         c.close()
+
+
+def test_batch_at_full_mixed_sizes_matches_oracle():
+    """Controllers of the mixed batch's largest sizes -- both models, K up to
+    8192, T up to 80, J up to 400 -- among them 256-sample tiles whose noise
+    does not fit in LDS and is drawn again in the batched kernel's epilogue:
+    each equals its standalone run bit for bit, on two steps, and matches the
+    oracle's iteration at the first (threaded oracle)."""
+    from paper_2504_06437_amd.controller import Batch
+    rng = np.random.Generator(np.random.PCG64(61))
+    shapes = [("quad6", 8192, 80, 400, 256), ("car", 8192, 80, 400, 0), ("car", 6000, 64, 250, 256),
+              ("quad6", 3000, 45, 180, 0), ("car", 700, 20, 10, 0), ("quad6", 8100, 77, 399, 128)]
+    wls = []
+    for i, (m, K, T, J, S) in enumerate(shapes):
+        wl = W.mixed_controller(rng, 700 + i, K=K, T=T, J=J, model=m)
+        wl["U0"] = W.random_controls(rng, T, 0.2)
+        wl["params"]["tile_samples"] = S
+        wls.append(wl)
+    alone = [_make(wl) for wl in wls]
+    mixed = [_make(wl) for wl in wls]
+    batch = Batch(mixed)
+    redrawn = 0
+    for step in range(2):
+        states = [c.get_state() for c in mixed]
+        u_b, sts = batch.step([wl["x0"] for wl in wls])
+        assert np.all(sts == 0)
+        for i, (a, m, wl) in enumerate(zip(alone, mixed, wls)):
+            np.testing.assert_array_equal(a.step(wl["x0"]), u_b[i])
+            np.testing.assert_array_equal(a.costs(), m.costs())
+            np.testing.assert_array_equal(a.controls(), m.controls())
+            if step == 0:
+                p = f32_params(wl["params"])
+                ref = oracle.step(p, oracle.World.from_workload(wl), wl["x0"], states[i]["U"], wl["x_ref"], 1.0,
+                                  states[i]["counter"])
+                assert ref["status"] == 0
+                S = m.costs()
+                bound = 1e-4 * np.maximum(np.abs(ref["S"]), 1.0) + 1e-5 * ref["sens"]
+                assert np.all(np.abs(S - ref["S"]) <= bound), f"controller {i}"
+                scale = np.asarray(p["sigma"])
+                for key, got in (("Ustar", m.last_optimal()), ("Unext", m.controls())):
+                    assert np.all(np.abs(got - ref[key]) <= 1e-4 * (np.abs(ref[key]) + scale)), f"{key} {i}"
+                np.testing.assert_allclose(m.weights(), ref["w"], rtol=0, atol=1e-4 * ref["w"].max())
+                info = m.info()
+                redrawn += int(info["noise_kept"] == 0)
+    assert redrawn >= 2
+    batch.close()
+    for c in alone + mixed:
+        c.close()

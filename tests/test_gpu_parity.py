@@ -89,10 +89,12 @@ def _check(gpu: dict, ref: dict, p: dict, S_e=1.0, what=""):
     assert np.all(d <= TOL_U * (np.abs(ref["u0"]) + scale)), f"{what} u0"
 
 
-def _gpu_outputs(c, u0):
-    return {"S": c.costs(), "w": c.weights(), "du": c.noise().astype(np.float64),
-            "Ustar": c.last_optimal().astype(np.float64), "Unext": c.controls().astype(np.float64),
-            "u0": np.asarray(u0, dtype=np.float64)}
+def _gpu_outputs(c, u0, with_noise=True):
+    g = {"S": c.costs(), "w": c.weights(), "Ustar": c.last_optimal().astype(np.float64),
+         "Unext": c.controls().astype(np.float64), "u0": np.asarray(u0, dtype=np.float64)}
+    if with_noise:
+        g["du"] = c.noise().astype(np.float64)
+    return g
 
 
 def _one_iteration(wl, S_e=1.0, **over):
@@ -241,43 +243,30 @@ def test_full_size_vehicle_workload():
     assert info["tiles"] >= 1
 
 
-def test_full_size_quadrotor_with_costmap_sampled():
-    """Quadrotor, K=16384, T=100, 400 obstacles + 512x512 costmap, FP64
-    normaliser: Philox words of sampled (k, t), the costs of 64 sampled
-    samples by the oracle's rollout, and the weights and update given the
-    GPU's own costs and noise through the oracle's softmax and update."""
+def test_full_size_quadrotor_with_costmap():
+    """Quadrotor at scale, K=16384, T=100, 400 obstacles + 512x512 costmap,
+    FP64 normaliser, in the launch configuration the benchmark times (no
+    noise export): every sample's cost, the weights, U*, the shifted U and
+    u0 against the oracle's own iteration (threaded over samples), and the
+    Philox words of sampled (k, t)."""
     wl = W.quad_large()
-    c, p = _ctrl(wl)
-    pf = f32_params(p)
+    c, p = _ctrl(wl, export_noise=False)
     st = c.get_state()
     u0 = c.step(wl["x0"])
     info = c.info()
     assert info["status"] == 0 and info["fp64_tiles"] == info["tiles"]
-    S, w, du, Us = c.costs(), c.weights(), c.noise().astype(np.float64), c.last_optimal().astype(np.float64)
+    g = _gpu_outputs(c, u0, with_noise=False)
     words = c.philox_words(st["counter"])
-    rng = np.random.Generator(np.random.PCG64(11))
-    ks = np.sort(rng.choice(p["K"], size=64, replace=False))
-    for k in ks[:8]:
+    for k in (0, 1, 4097, 9999, 16383):
         for t in (0, 57, 99):
             want = oracle.philox([k, t, st["counter"] & 0xFFFFFFFF, st["counter"] >> 32],
                                  [p["seed"] & 0xFFFFFFFF, p["seed"] >> 32])
             assert list(words[k, t]) == want
-    world = _world(wl)
-    du_ref = oracle.noise(dict(pf, K=p["K"]), st["counter"])
-    beta_d = oracle.fused_barrier(pf, world, wl["x_ref"][-1])
-    S_ref, sens = np.zeros(len(ks)), np.zeros(len(ks))
-    for i, k in enumerate(ks):
-        S_ref[i], _, _, _, sens[i] = oracle.rollout_one(pf, world, wl["x0"], st["U"], du_ref[k], wl["x_ref"], 1.0,
-                                                        beta_d, with_clearance=True)
-    _check_costs(S[ks], S_ref, sens, "sampled costs")
-    np.testing.assert_allclose(du[ks], du_ref[ks], rtol=1e-5, atol=1e-6 * 0.5)
-    st_w, w_ref, _, _ = oracle.weights(S, p["lambda"])
-    big = w_ref >= 1e-8 * w_ref.max()
-    assert np.max(np.abs(w[big] - w_ref[big]) / w_ref[big]) <= 1e-5
-    Us_ref = oracle.update(st["U"], du, w)
-    assert np.all(np.abs(Us - Us_ref) <= TOL_U * (np.abs(Us_ref) + 0.5))
-    assert abs(w.sum() - 1.0) < 1e-9
-    np.testing.assert_allclose(u0, Us[0], rtol=0, atol=0)
+    ref = oracle.step(f32_params(p), _world(wl), wl["x0"], st["U"], wl["x_ref"], 1.0, st["counter"])
+    assert ref["status"] == 0
+    _check(g, ref, p, what="full-size quadrotor")
+    assert abs(g["w"].sum() - 1.0) < 1e-9
+    np.testing.assert_array_equal(g["u0"], g["Ustar"][0])
     c.close()
 
 

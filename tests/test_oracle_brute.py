@@ -120,10 +120,15 @@ def test_brute_force_cases_exercise_every_term(orc):
 
 def test_oracle_matches_brute_force_other_settings(orc):
     """Zero-initialised last control, a zero-sigma channel, a wide
-    log-normal spread and a large step counter."""
+    log-normal spread and a large step counter; a barrier cap and a
+    sensitivity reach wide enough that some terms straddle the cap."""
     p, world, x0, U, x_ref, S_e = _case("quad6", 3, True)
     p.update(init_mode="zero", sigma=[0.0, 0.9], mu_ln=0.3, sigma_ln=0.8, seed=0xFEDCBA9876543210)
     _compare(orc, (p, world, x0, U, x_ref, 2.5), counter=(1 << 40) + 77)
+    for model in ("quad6", "car"):
+        p, world, x0, U, x_ref, S_e = _case(model, 1, True)
+        p.update(h_eps=0.2, sens_reach=0.05)
+        _compare(orc, (p, world, x0, U, x_ref, S_e))
 
 
 # ---------------------------------------------------------------------------
@@ -202,6 +207,38 @@ def test_sensitivity_bounds_every_move_with_many_points_and_a_costmap(orc):
     assert abs(np.abs(g).sum() - orc.barrier_sensitivity(p1, world, xs)) <= 1e-5 * np.abs(g).sum()
 
 
+@pytest.mark.parametrize("h0", [-0.3, 0.99e-4, 1.005e-4, 3e-4, 0.02, 0.7])
+def test_sensitivity_bounds_finite_moves_within_its_reach(orc, h0):
+    """With a reach r, every move of the shape points by at most r per
+    coordinate changes the fused barrier by at most r x sensitivity -- also
+    when the move crosses the cap h = h_eps, where the first-order bound is
+    zero on one side."""
+    rng = np.random.Generator(np.random.PCG64(int(abs(h0) * 1e7) + 3))
+    reach = 1e-5
+    p = W.base_params("car", 1, 1)
+    p.update(shape=[[0.0, 0.0], [0.3, -0.2]], sens_reach=reach)
+    r = 0.8
+    d0 = math.sqrt(r * r + h0)
+    ang = 0.4
+    world = orc.World(np.array([[d0 * math.cos(ang), d0 * math.sin(ang), r], [4.0, 3.0, 0.6]]))
+    x = [0.0, 0.0, 0.0, 0.0]
+    assert abs(orc.clearance(dict(p, shape=[[0.0, 0.0]]), world, x) - h0) < 1e-12
+    sens = orc.barrier_sensitivity(p, world, x)
+    B0 = orc.fused_barrier(p, world, x)
+    worst = 0.0
+    for _ in range(400):
+        d = rng.choice([-1.0, 1.0], size=(2, 2)) * reach * rng.uniform(0.5, 1.0, size=(2, 2))
+        moved = [[a + d[i, 0], b + d[i, 1]] for i, (a, b) in enumerate(p["shape"])]
+        worst = max(worst, abs(orc.fused_barrier(dict(p, shape=moved), world, x) - B0))
+    assert worst <= reach * sens * (1 + 1e-9)
+    if 0 < h0 - p["h_eps"] < 1e-5 or 0 < p["h_eps"] - h0 < 1e-5:
+        # near the cap the bound is not vacuous: some move reaches a good part of it
+        assert worst >= 0.05 * reach * sens
+    if h0 < 0:
+        # deep inside an obstacle the term is flat: only the other terms count
+        assert sens < 1e4
+
+
 def test_clearance_is_the_direct_minimum(orc):
     rng = np.random.Generator(np.random.PCG64(8))
     p = W.base_params("quad6", 1, 1)
@@ -277,8 +314,8 @@ MUTANTS = [
      "phi += cfg->Q[a] * (x[a] - refT[a]) * (x[a] - refT[a]);"),
     ("indicator inverted", "return orc_clearance(cfg, w, x) < 0.0 ? 1 : 0;", "return orc_clearance(cfg, w, x) > 0.0 ? 1 : 0;"),
     ("normal sampling keeps the log-normal factor", "if (cfg->sampling == ORC_SAMPLE_NORMAL) {", "if (0) {"),
-    ("sensitivity factor", "if (h > cfg->h_eps) s += 2.0 * (fabs(dx) + fabs(dy)) / (h * h);",
-     "if (h > cfg->h_eps) s += (fabs(dx) + fabs(dy)) / (h * h);"),
+    ("sensitivity factor", "double g = 2.0 * (fabs(dx) + fabs(dy));", "double g = fabs(dx) + fabs(dy);"),
+    ("sensitivity slope", "return 1.0 / (lo * lo);", "return 1.0 / lo;"),
     ("obstacle radius", "double h = dx * dx + dy * dy - r * r;\n            sum += barrier(cfg, h);",
      "double h = dx * dx + dy * dy - r;\n            sum += barrier(cfg, h);"),
 ]
