@@ -1,6 +1,5 @@
 // Batched iteration of many controllers in one persistent launch, captured
-// once into a HIP graph, plus the per-shape tile autotuner and the library's
-// global error slot.
+// once into a HIP graph, and the library's global error slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,111 +22,6 @@ thread_local std::string g_error;
 
 void set_global_error(const std::string& s) { g_error = s; }
 const char* global_error() { return g_error.c_str(); }
-
-// ---------------------------------------------------------------------------
-// Autotuner: samples per tile S for a (model, K, T, J, P, costmap) shape.
-// Candidates are timed on the controller's own data with scratch outputs; the
-// choice is cached per shape for the process, so every controller of one
-// shape (alone or in a batch) runs the same tile shape.
-// ---------------------------------------------------------------------------
-namespace {
-
-using ShapeKey = std::tuple<int, int, int, int, int, int>;
-std::mutex g_tune_mu;
-std::map<ShapeKey, int> g_tune_cache;
-
-bool autotune_enabled()
-{
-    const char* v = std::getenv("MPPI_AUTOTUNE");
-    return !(v && v[0] == '0');
-}
-
-// Time the rollout kernel of `h` with S samples per tile; returns ms or -1.
-float time_rollout(mppi_ctrl* h, int S, int reps)
-{
-    DevParams q = h->p;
-    q.spt = S;
-    q.tiles = (q.K + q.spt - 1) / q.spt;
-    const size_t tiles = (size_t)q.tiles;
-    void* buf = nullptr;
-    const size_t bytes = sizeof(CtrlState) + sizeof(float) * ((size_t)q.T * kM * q.Kp + 3 * (size_t)q.Kp) +
-                         sizeof(double) * (3 * tiles + 2 * (size_t)q.T * tiles) + sizeof(int32_t) * tiles + 256;
-    if (hipMalloc(&buf, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return -1.0f;
-    }
-    char* c = static_cast<char*>(buf);
-    auto take = [&](size_t n) {
-        char* r = c;
-        c += (n + 15) & ~(size_t)15;
-        return r;
-    };
-    q.st = reinterpret_cast<CtrlState*>(take(sizeof(CtrlState)));
-    q.du = reinterpret_cast<float*>(take(sizeof(float) * (size_t)q.T * kM * q.Kp));
-    q.S = reinterpret_cast<float*>(take(sizeof(float) * 2 * (size_t)q.Kp));
-    q.e = reinterpret_cast<float*>(take(sizeof(float) * (size_t)q.Kp));
-    q.rho_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
-    q.eta_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
-    q.f_b = reinterpret_cast<double*>(take(sizeof(double) * tiles));
-    q.flag_b = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * tiles));
-    q.partN = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)q.T * tiles));
-    q.res = nullptr;
-    float best = -1.0f;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-    StepArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.parity = h->iter & 1u;
-    for (int r = 0; ok && r <= reps; ++r) {
-        // a fresh copy of the real state for every run
-        ok = hipMemcpyAsync(q.st, h->p.st, sizeof(CtrlState), hipMemcpyDeviceToDevice, h->stream) == hipSuccess;
-        ok = ok && hipEventRecord(e0, h->stream) == hipSuccess;
-        ok = ok && launch_rollout(q, a, h->stream) == hipSuccess;
-        ok = ok && hipEventRecord(e1, h->stream) == hipSuccess;
-        ok = ok && hipEventSynchronize(e1) == hipSuccess;
-        float ms = 0.0f;
-        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        if (ok && r > 0 && (best < 0 || ms < best)) best = ms;   // r = 0 warms up
-    }
-    if (!ok) (void)hipGetLastError();
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(buf);
-    return ok ? best : -1.0f;
-}
-
-}  // namespace
-
-namespace dbas {
-
-int choose_tile_samples(mppi_ctrl* h)
-{
-    const DevParams& p = h->p;
-    const ShapeKey key{p.model, p.K, p.T, p.J, p.P, p.sdf != nullptr ? 1 : 0};
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) return it->second;
-    }
-    int S = heuristic_tile_samples(p.K, p.J, p.T, p.n);
-    if (autotune_enabled() && p.J > 0 && h->sync() == MPPI_OK) {
-        float best = -1.0f;
-        for (int cand : {16, 32, 64, 128, 256}) {
-            if (tile_chunk_steps(p.J, p.T, p.n, cand) == 0 || (p.K + cand - 1) / cand > kMaxTiles) continue;
-            const float ms = time_rollout(h, cand, 3);
-            if (ms > 0 && (best < 0 || ms < best * 0.97f)) {
-                best = ms;
-                S = cand;
-            }
-        }
-    }
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache.emplace(key, S);
-    return g_tune_cache[key];
-}
-
-}  // namespace dbas
 
 // ---------------------------------------------------------------------------
 // Batch

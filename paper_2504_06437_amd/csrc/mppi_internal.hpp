@@ -220,6 +220,18 @@ __host__ __device__ inline int tile_chunk_steps(int J, int T, int n, int S)
     return (int)tc;
 }
 
+// Does a tile of S samples fit the rollout's LDS budget: at least one horizon
+// step per chunk and, with Savitzky-Golay smoothing (sgf_m > 0), room for the
+// 2T FP64 update sums that the tile smooths in the space of its spent chunk
+// inputs (two buffers of tc x S float4)?  Every place that picks or accepts a
+// tile shape asks this one question.
+__host__ __device__ inline bool tile_fits(int J, int T, int n, int S, int sgf_m)
+{
+    const int tc = tile_chunk_steps(J, T, n, S);
+    if (tc == 0) return false;
+    return sgf_m <= 0 || (size_t)2 * T * 8 <= (size_t)2 * tc * S * 16;
+}
+
 // Does the tile keep its whole noise (T x S float2) in LDS for the epilogue,
 // or draw it again there?
 __host__ __device__ inline bool tile_keeps_noise(int J, int T, int n, int S)

@@ -302,27 +302,32 @@ int mppi_ctrl::write_state_field(size_t offset, const void* src, size_t bytes)
 namespace dbas {
 
 // Samples per tile: the largest tile (at most 64) that still gives every CU of
-// the chip a tile, and whose chunk fits the LDS budget.  Used when the
-// configuration leaves tile_samples at 0 and no measured choice is cached.
-int heuristic_tile_samples(int K, int J, int T, int n)
+// the chip a tile, and that fits the LDS budget (tile_fits).  Used when the
+// configuration leaves tile_samples at 0 and no measured choice is known.
+// Returns 0 when no tile shape fits.
+int heuristic_tile_samples(int K, int J, int T, int n, int sgf_m)
 {
     int S = 16;
     while (S < 64 && (long)K / (2 * S) >= 256) S *= 2;
-    while (S > 16 && tile_chunk_steps(J, T, n, S) == 0) S /= 2;
     while (S < kMaxTile && (K + S - 1) / S > kMaxTiles) S *= 2;
-    return S;
+    for (int c = S; c >= 16; c /= 2)
+        if (tile_fits(J, T, n, c, sgf_m) && (K + c - 1) / c <= kMaxTiles) return c;
+    for (int c = S * 2; c <= kMaxTile; c *= 2)
+        if (tile_fits(J, T, n, c, sgf_m) && (K + c - 1) / c <= kMaxTiles) return c;
+    return 0;
 }
+
+// Is there any tile shape for these sizes?
+bool any_tile_fits(int K, int J, int T, int n, int sgf_m) { return heuristic_tile_samples(K, J, T, n, sgf_m) != 0; }
 
 }  // namespace dbas
 
 int mppi_ctrl::configure_tiles(int S)
 {
-    if (!tile_samples_supported(S) || tile_chunk_steps(p.J, cfg.T, p.n, S) == 0)
-        return fail(MPPI_E_INVALID, "J=%d obstacles with T=%d do not fit the rollout's LDS budget at %d samples per tile",
-                    p.J, cfg.T, S);
-    // the tile smooths its 2T partial sums (FP64) in the space of its chunk inputs
-    if (p.sgf_m > 0 && (size_t)2 * cfg.T * 8 > (size_t)2 * tile_chunk_steps(p.J, cfg.T, p.n, S) * S * 16)
-        return fail(MPPI_E_INVALID, "T=%d is too long to smooth within the LDS of a %d-sample tile", cfg.T, S);
+    if (!tile_samples_supported(S) || !tile_fits(p.J, cfg.T, p.n, S, p.sgf_m))
+        return fail(MPPI_E_INVALID,
+                    "J=%d obstacles with T=%d%s do not fit the rollout's LDS budget at %d samples per tile", p.J,
+                    cfg.T, p.sgf_m > 0 ? " and smoothing" : "", S);
     p.spt = S;
     p.tiles = (cfg.K + S - 1) / S;
     if (p.tiles > kMaxTiles) return fail(MPPI_E_INVALID, "K=%d needs more than %d tiles of %d samples", cfg.K, kMaxTiles, S);
@@ -435,7 +440,8 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 
-    st = h->configure_tiles(cfg->tile_samples ? cfg->tile_samples : heuristic_tile_samples(K, 0, T, n));
+    st = h->configure_tiles(cfg->tile_samples ? cfg->tile_samples
+                                              : heuristic_tile_samples(K, 0, T, n, cfg->sgf_half_window));
     if (st) {
         set_global_error("mppi_create: " + h->err);
         delete h;
@@ -509,10 +515,10 @@ extern "C" void mppi_destroy(mppi_t* h) { delete h; }
 // and the configuration did not fix it.
 int mppi_ctrl::retile()
 {
-    if (tiles_fixed) return MPPI_OK;
+    if (tiles_fixed) return tile_fits(p.J, cfg.T, p.n, p.spt, p.sgf_m) ? MPPI_OK : configure_tiles(p.spt);
     const int S = choose_tile_samples(this);
-    if (S == p.spt) return MPPI_OK;
-    if (tile_chunk_steps(p.J, cfg.T, p.n, S) == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
+    if (S == 0) return fail(MPPI_E_INVALID, "no tile shape fits the LDS budget");
+    if (S == p.spt) return configure_tiles(S);
     if (external_scratch) {
         ++version;
         return configure_tiles(S);
@@ -527,8 +533,11 @@ int mppi_ctrl::retile()
     (void)hipFree(p.flag_b);
     allocations.erase(std::find(allocations.begin(), allocations.end(), (void*)p.partN));
     (void)hipFree(p.partN);
-    configure_tiles(S);
+    p.rho_b = p.eta_b = p.f_b = p.partN = nullptr;
+    p.flag_b = nullptr;
     ++version;
+    const int st = configure_tiles(S);
+    if (st) return st;
     return alloc_tile_buffers();
 }
 
@@ -537,8 +546,10 @@ extern "C" int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int3
     CHECK_HANDLE(h);
     if (J < 0 || J > MPPI_JMAX) return h->fail(MPPI_E_INVALID, "J=%d outside 0..%d", J, MPPI_JMAX);
     if (J > 0 && !cxcyr) return h->fail(MPPI_E_INVALID, "obstacles pointer is NULL");
-    if (tile_chunk_steps(J, h->cfg.T, h->p.n, h->tiles_fixed ? h->p.spt : 16) == 0)
-        return h->fail(MPPI_E_INVALID, "J=%d obstacles with T=%d exceed the rollout's LDS budget", J, h->cfg.T);
+    if (h->tiles_fixed ? !tile_fits(J, h->cfg.T, h->p.n, h->p.spt, h->p.sgf_m)
+                       : !any_tile_fits(h->cfg.K, J, h->cfg.T, h->p.n, h->p.sgf_m))
+        return h->fail(MPPI_E_INVALID, "J=%d obstacles with T=%d%s exceed the rollout's LDS budget", J, h->cfg.T,
+                       h->p.sgf_m > 0 ? " and smoothing" : "");
     std::vector<float> tmp;
     if (J > 0 && mem == MPPI_MEM_HOST) {
         if (!finite_all(cxcyr, (size_t)3 * J)) return h->fail(MPPI_E_INVALID, "non-finite obstacle");

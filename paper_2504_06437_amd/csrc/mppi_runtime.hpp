@@ -49,8 +49,10 @@ struct mppi_ctrl {
 
 namespace dbas {
 std::string validate_config(const mppi_config* c);
-int heuristic_tile_samples(int K, int J, int T, int n);
-// Samples per tile for this controller's (model, K, T, J, P, costmap): measured once per shape.
+int heuristic_tile_samples(int K, int J, int T, int n, int sgf_m);
+bool any_tile_fits(int K, int J, int T, int n, int sgf_m);
+// Samples per tile for this controller's (model, K, T, J, P, costmap,
+// smoothing); 0 when no tile shape fits.
 int choose_tile_samples(mppi_ctrl* h);
 int create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool external_scratch, mppi_ctrl** out);
 }  // namespace dbas

@@ -1,12 +1,68 @@
 """The mission harness with the HIP controller in the loop (Sec. VI set-up,
-synthetic layouts): five seeded experiments per mission.  The controller's
-arithmetic is deterministic, so the outcomes repeat; the assertions leave a
-margin of one run for the quadrotor, whose slow mission can time out."""
+synthetic layouts).
+
+* Parity, teacher-forced: along a closed-loop mission run (the paper's
+  settings: M = 1024, N = 20, its Sigma_u, mu = 0.4, adaptive exploration
+  on), every control step of the HIP controller is compared with the oracle's
+  iteration started from the same state, warm start, counter and S_e (noise,
+  costs, weights, U*, shifted U, u0, to the bars of test_gpu_parity), and the
+  exploration rate it sets for the next step with the oracle's (on the GPU's
+  own U*, with the cost tolerance carried through the logarithm).
+* Outcomes: five seeded experiments per mission.  The controller's
+  arithmetic is deterministic, so the outcomes repeat; the assertions leave a
+  margin of one run for the quadrotor, whose slow mission can time out.
+"""
+import math
+
+import numpy as np
 import pytest
 
+import oracle
+from conftest import SENS_REACH, f32_params
+from parity_checks import check
 from paper_2504_06437_amd import mission as M
+from paper_2504_06437_amd import plant
+from paper_2504_06437_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mission", [1, 2])
+def test_mission_steps_match_oracle_teacher_forced(mission):
+    from paper_2504_06437_amd.controller import Controller
+    wl = M.layout(mission, seed=0)
+    p = dict(wl["params"], export_noise=True)
+    c = Controller(p)
+    c.load_workload(wl)
+    pf = f32_params(p)
+    world = oracle.World.from_workload(wl)
+    x = np.asarray(wl["x0"], dtype=np.float32).copy()
+    mu = p["explore_mu"]
+    rates = []
+    for step in range(30):
+        xr = W.reference(wl, x)
+        c.set_reference(xr)
+        st = c.get_state()
+        u0 = c.step(x)
+        g = {"S": c.costs(), "w": c.weights(), "du": c.noise().astype(np.float64),
+             "Ustar": c.last_optimal().astype(np.float64), "Unext": c.controls().astype(np.float64),
+             "u0": np.asarray(u0, dtype=np.float64)}
+        ref = oracle.step(pf, world, x, st["U"], xr, float(np.float32(st["S_e"])), st["counter"])
+        assert ref["status"] == 0
+        check(g, ref, p, S_e=st["S_e"], what=f"mission {mission} step {step}")
+        info = c.info()
+        se_ref, cb_ref = oracle.exploration(pf, world, x, g["Ustar"], info["beta_d"], mu)
+        _, _, _, _, sens = oracle.rollout_one(pf, world, x, g["Ustar"], np.zeros_like(g["Ustar"]), xr, 1.0,
+                                              info["beta_d"], with_clearance=True)
+        tol_cb = 1e-4 * max(abs(cb_ref), 1.0) + SENS_REACH * sens
+        assert abs(info["cost_b"] - cb_ref) <= tol_cb, (step, info["cost_b"], cb_ref, tol_cb)
+        tol_se = mu * tol_cb / (math.e + max(cb_ref, 0.0)) + 1e-6 * se_ref
+        assert abs(info["S_e"] - se_ref) <= tol_se, (step, info["S_e"], se_ref)
+        rates.append(info["S_e"])
+        x = plant.advance(p, x, u0)
+    c.close()
+    # the exploration rate did adapt along the run
+    assert max(rates) > min(rates)
 
 
 @pytest.mark.parametrize("mission,min_success", [(1, 80.0), (2, 100.0), (3, 100.0)])
