@@ -259,6 +259,53 @@ int mppi_profile_enable(mppi_t* h, int32_t every);
 int mppi_profile_read(mppi_t* h, mppi_profile* out);
 
 /* ------------------------------------------------------------------------ */
+/* One iteration without a handle and without allocating: for callers that    */
+/* cannot allocate device memory -- code under HIP graph capture, tight       */
+/* serving loops, harnesses that forbid allocation.                           */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the library's static per-GPU scratch array (held by each GPU the
+ * library runs on until the process ends). */
+#define MPPI_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* The world of one iteration, in caller-owned device memory (read only). */
+typedef struct mppi_problem {
+    int32_t J;                     /* circular obstacles, 0..MPPI_JMAX */
+    const float* obs;              /* device [J][3] (cx, cy, r); NULL when J = 0 */
+    int32_t map_w, map_h;          /* costmap size (>= 2 each) when sdf is not NULL */
+    float map_x0, map_y0, map_res; /* costmap placement, as in mppi_set_costmap */
+    const float* sdf;              /* device [map_h][map_w] signed distances, or NULL */
+    const float* x_ref;            /* device [T+1][n] reference, as in mppi_set_reference */
+} mppi_problem;
+
+/* The iteration mppi_step runs for a controller of configuration `cfg`
+ * whose warm start is U (device float[T][2]), Philox step counter `counter`
+ * and exploration rate S_e, on the world `prob`, from state x0 (device
+ * float[n]).  Writes (device buffers): U*[T][2] before the shift, the
+ * shifted warm start Unext[T][2] (Algorithm 1's closing loop; equal to U
+ * when the iteration fails NUMERIC), and, when not NULL, u0[2] and the
+ * iteration's status (int32: MPPI_OK or MPPI_E_NUMERIC).  The next
+ * iteration's counter is counter + 1 after MPPI_OK.
+ * Stream-ordered on `stream` (hipStream_t, NULL: the null stream) of GPU
+ * `device`; returns without waiting.  Allocates nothing: the per-iteration
+ * scratch (costs, exponentials, tile partials, iteration state) is the
+ * library's static array of MPPI_NOALLOC_SCRATCH_BYTES on that GPU, shared by
+ * every call there, so calls on one GPU must not overlap (one stream, or a
+ * wait in between); kernels only, no memset or copy, so a capture records it.
+ * The tile size is cfg->tile_samples, or the heuristic one when it is 0 (no
+ * timing).  Results equal mppi_step's for the same configuration and tile
+ * size bit for bit.
+ * Errors (nothing launched): INVALID for a bad configuration, a NULL required
+ * pointer, adaptive_explore / sgf_half_window / export_noise set (they need a
+ * handle), a world or horizon that does not fit the rollout's LDS, or a
+ * scratch need (about 12 K + 16 T K / S + 28 K / S bytes) above
+ * MPPI_NOALLOC_SCRATCH_BYTES; DEVICE for a HIP failure.  mppi_last_error(NULL)
+ * describes it.  Obstacle and map values are not checked (device memory). */
+int mppi_step_noalloc(const mppi_config* cfg, const mppi_problem* prob, int32_t device, void* stream,
+                      const float* x0, const float* U, uint64_t counter, float S_e, float* Ustar, float* Unext,
+                      float* u0, int32_t* status);
+
+/* ------------------------------------------------------------------------ */
 /* Batched iteration: many controllers (any mix of models, K, T, J) stepped  */
 /* by one persistent kernel, captured once in a HIP graph.  Controllers stay */
 /* owned by the caller and must outlive the batch; each one's tile shape is   */

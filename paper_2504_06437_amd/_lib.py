@@ -30,8 +30,10 @@ EXPORTS = [
     "mppi_batch_create", "mppi_batch_destroy", "mppi_batch_step", "mppi_batch_last_error",
     "mppi_server_create", "mppi_server_destroy", "mppi_server_add_robot", "mppi_server_submit",
     "mppi_server_poll", "mppi_server_wait", "mppi_server_now", "mppi_server_get_stats",
-    "mppi_server_get_robot", "mppi_server_last_error",
+    "mppi_server_get_robot", "mppi_server_last_error", "mppi_step_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class MppiError(RuntimeError):
@@ -77,6 +79,12 @@ class StepInfo(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("dropped", ctypes.c_int64), ("rollout_ms", ctypes.c_double),
                 ("update_ms", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int32), ("obs", ctypes.c_void_p), ("map_w", ctypes.c_int32),
+                ("map_h", ctypes.c_int32), ("map_x0", ctypes.c_float), ("map_y0", ctypes.c_float),
+                ("map_res", ctypes.c_float), ("sdf", ctypes.c_void_p), ("x_ref", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -144,6 +152,8 @@ def load(path: str = LIB_PATH):
         "mppi_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
         "mppi_server_get_robot": (i32, [vp, i32, fp, ctypes.POINTER(u64)]),
         "mppi_server_last_error": (ctypes.c_char_p, [vp]),
+        "mppi_step_noalloc": (i32, [ctypes.POINTER(Config), ctypes.POINTER(Problem), i32, vp, vp, vp, u64,
+                                    ctypes.c_float, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

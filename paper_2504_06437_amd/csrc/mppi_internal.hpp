@@ -70,6 +70,8 @@ struct DevParams {
     const float* sdf;        // [map_h][map_w] or null
     const float* xref;       // [T+1][n] world frame
     float* U;                // [2][T][2] warm start, double-buffered by iteration parity
+    float* Unext;            // [T][2] where the update writes the shifted warm start instead of the
+                             //   other half of U (null: the other half; the handle-free entry point)
     float* Ustar;            // [T][2] optimal sequence of the last iteration (before the shift)
     float* du;               // [T][2][Kp] noise (only with export_noise)
     float* S;                // [2][Kp] compensated cost: hi at [k], lo at [Kp + k]
@@ -91,6 +93,7 @@ struct StepArgs {
     uint32_t parity;         // iterations run & 1: the half of U that holds the warm start
     uint32_t mark;           // 1: publish u0, status and the completion mark to the host
                              //    at once (system-scope fences), for a host thread spinning
+    int32_t* status_dev;     // optional device copy of the iteration's status
 };
 
 // Per-step input of one controller of a batch (staged by the host).

@@ -27,15 +27,15 @@ namespace {
 // loop) into the other half of the double buffer and u0*; the workgroup of
 // row 0 also records the iteration in the controller's state.
 // ---------------------------------------------------------------------------
-__device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, bool mark, double* sf,
-                            double* slots)
+__device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, int32_t* status_dev,
+                            bool mark, double* sf, double* slots)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
     const int T = p.T, nt = p.tiles;
     CtrlState* st = p.st;
     const float* Uin = p.U + (size_t)(parity & 1u) * T * kM;
-    float* Uout = p.U + (size_t)((parity + 1u) & 1u) * T * kM;
+    float* Uout = p.Unext ? p.Unext : p.U + (size_t)((parity + 1u) & 1u) * T * kM;
     const bool first = row0 == 0;
 
     // Every load that does not depend on the merge is issued first: this
@@ -126,6 +126,7 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
             st->eta = eta;
             st->status = status;
             st->fp64_tiles = (int32_t)n64s;
+            if (status_dev) *status_dev = status;
             const uint32_t it = st->iter + 1u;
             st->iter = it;
             if (p.res) {
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
 {
     __shared__ double sf[kMaxTiles];
     __shared__ double slots[2 * kUpdWaves];
-    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.mark != 0, sf, slots);
+    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.status_dev, a.mark != 0, sf, slots);
 }
 
 // One workgroup per (controller, four control rows) of the batch.
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __r
     __shared__ double sf[kMaxTiles];
     __shared__ double slots[2 * kUpdWaves];
     const RowUnit ru = units[blockIdx.x];
-    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, false, sf,
-                slots);
+    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, nullptr, false,
+                sf, slots);
 }
 
 __global__ __launch_bounds__(kExpBlock) void k_explore(DevParams p, StepArgs a)

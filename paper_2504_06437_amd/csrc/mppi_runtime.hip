@@ -348,48 +348,11 @@ int mppi_ctrl::alloc_tile_buffers()
     return MPPI_OK;
 }
 
-extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_t** out)
-{
-    return create_ctrl(cfg, dev, false, out);
-}
+namespace dbas {
 
-// external_scratch: leave the per-iteration sample buffers (noise, costs,
-// exponentials, tile partials) unallocated; the owner (the server) supplies
-// them per launch from its own pool.
-int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool external_scratch, mppi_ctrl** out)
+// The kernel parameters a configuration fixes (no buffers, no obstacles).
+void params_from_config(const mppi_config* cfg, DevParams& p)
 {
-    if (!out) return MPPI_E_INVALID;
-    *out = nullptr;
-    std::string why = validate_config(cfg);
-    if (!why.empty()) {
-        set_global_error("mppi_create: " + why);
-        return MPPI_E_INVALID;
-    }
-    mppi_ctrl* h = new (std::nothrow) mppi_ctrl();
-    if (!h) return MPPI_E_NOMEM;
-    h->cfg = *cfg;
-    h->external_scratch = external_scratch;
-    h->device = dev ? dev->device : 0;
-    int st = MPPI_OK;
-    hipError_t e = hipSetDevice(h->device);
-    if (e != hipSuccess) {
-        set_global_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
-        delete h;
-        return MPPI_E_DEVICE;
-    }
-    if (dev && dev->stream) {
-        h->stream = static_cast<hipStream_t>(dev->stream);
-    } else {
-        e = hipStreamCreate(&h->stream);
-        if (e != hipSuccess) {
-            set_global_error(std::string("hipStreamCreate: ") + hipGetErrorString(e));
-            delete h;
-            return MPPI_E_DEVICE;
-        }
-        h->own_stream = true;
-    }
-
-    DevParams& p = h->p;
     std::memset(&p, 0, sizeof p);
     const int K = cfg->K, T = cfg->T, n = state_dim(cfg->model);
     p.model = cfg->model;
@@ -439,6 +402,54 @@ int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool exter
     p.sgf_m = cfg->sgf_half_window;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
+}
+
+}  // namespace dbas
+
+extern "C" int mppi_create(const mppi_config* cfg, const mppi_device* dev, mppi_t** out)
+{
+    return create_ctrl(cfg, dev, false, out);
+}
+
+// external_scratch: leave the per-iteration sample buffers (noise, costs,
+// exponentials, tile partials) unallocated; the owner (the server) supplies
+// them per launch from its own pool.
+int dbas::create_ctrl(const mppi_config* cfg, const mppi_device* dev, bool external_scratch, mppi_ctrl** out)
+{
+    if (!out) return MPPI_E_INVALID;
+    *out = nullptr;
+    std::string why = validate_config(cfg);
+    if (!why.empty()) {
+        set_global_error("mppi_create: " + why);
+        return MPPI_E_INVALID;
+    }
+    mppi_ctrl* h = new (std::nothrow) mppi_ctrl();
+    if (!h) return MPPI_E_NOMEM;
+    h->cfg = *cfg;
+    h->external_scratch = external_scratch;
+    h->device = dev ? dev->device : 0;
+    int st = MPPI_OK;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) {
+        set_global_error(std::string("hipSetDevice: ") + hipGetErrorString(e));
+        delete h;
+        return MPPI_E_DEVICE;
+    }
+    if (dev && dev->stream) {
+        h->stream = static_cast<hipStream_t>(dev->stream);
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            set_global_error(std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            delete h;
+            return MPPI_E_DEVICE;
+        }
+        h->own_stream = true;
+    }
+
+    DevParams& p = h->p;
+    params_from_config(cfg, p);
+    const int K = cfg->K, T = cfg->T, n = state_dim(cfg->model);
 
     st = h->configure_tiles(cfg->tile_samples ? cfg->tile_samples
                                               : heuristic_tile_samples(K, 0, T, n, cfg->sgf_half_window));

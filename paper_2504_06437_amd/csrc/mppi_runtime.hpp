@@ -49,6 +49,7 @@ struct mppi_ctrl {
 
 namespace dbas {
 std::string validate_config(const mppi_config* c);
+void params_from_config(const mppi_config* cfg, DevParams& p);
 int heuristic_tile_samples(int K, int J, int T, int n, int sgf_m);
 bool any_tile_fits(int K, int J, int T, int n, int sgf_m);
 // Samples per tile for this controller's (model, K, T, J, P, costmap,
