@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MPPI_ABI_VERSION 1u
+#define MPPI_ABI_VERSION 2u
 #define MPPI_M 2          /* inputs per model */
 #define MPPI_NMAX 6       /* largest state dimension */
 #define MPPI_PMAX 16      /* most body shape points */
@@ -63,6 +63,10 @@ typedef enum { MPPI_QUAD6 = 0, MPPI_QUAD5 = 1, MPPI_CAR = 2 } mppi_model;
 typedef enum { MPPI_NORM_AUTO = 0, MPPI_NORM_ON = 1, MPPI_NORM_OFF = 2 } mppi_normaliser;
 typedef enum { MPPI_INIT_REPEAT = 0, MPPI_INIT_ZERO = 1 } mppi_init_mode;
 typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
+/* Sampling law of the perturbations (Sec. IV-C; Sec. V's Vanilla baseline). */
+typedef enum { MPPI_SAMPLE_NLN = 0, MPPI_SAMPLE_NORMAL = 1 } mppi_sampling;
+/* Collision term of the running cost (Sec. IV-A). */
+typedef enum { MPPI_COST_DBAS = 0, MPPI_COST_INDICATOR = 1 } mppi_cost_mode;
 
 /*
  * Problem statement (Sec. III-A eq. mppi; Algorithm 1's Require list; Sec.
@@ -104,6 +108,19 @@ typedef enum { MPPI_MEM_HOST = 0, MPPI_MEM_DEVICE = 1 } mppi_mem;
  *    window; near the ends of the horizon the window is the first (last)
  *    2m+1 steps.  m = 0 (default) applies no smoothing; m > 0 needs
  *    T >= 2m+1, m <= 16 and 0 <= p <= min(2m, 8).
+ *  - sampling, cost_mode, collision_weight: the paper's controller and its
+ *    two baselines (Sec. IV-A, Sec. V and its mission table) are modes of the
+ *    same iteration.  sampling = MPPI_SAMPLE_NLN (default) draws the normal x
+ *    log-normal mixture; MPPI_SAMPLE_NORMAL draws its normal part alone,
+ *    du = sqrt(S_e) sigma_c n (Vanilla MPPI).  cost_mode = MPPI_COST_DBAS
+ *    (default) carries the barrier state and adds R_B beta_t; with
+ *    MPPI_COST_INDICATOR there is no barrier state and every step adds
+ *    collision_weight (finite, >= 0) when some shape point violates a
+ *    constraint (h < 0 for a circle or the costmap), the weighted indicator
+ *    of Vanilla MPPI and Log-MPPI.  Vanilla MPPI = (NORMAL, INDICATOR),
+ *    Log-MPPI = (NLN, INDICATOR), DBaS-Log-MPPI = (NLN, DBAS) with
+ *    adaptive_explore.  The indicator mode does not take adaptive_explore
+ *    (its rate follows the barrier cost).
  */
 typedef struct mppi_config {
     uint32_t abi_version;          /* must be MPPI_ABI_VERSION */
@@ -127,6 +144,9 @@ typedef struct mppi_config {
     float explore_mu;              /* coarseness factor mu in (0,1) of S_e = mu ln(e + C_B) */
     int32_t sgf_half_window;       /* Savitzky-Golay half window m (0: no smoothing) */
     int32_t sgf_order;             /* Savitzky-Golay polynomial order p, 0 <= p <= min(2m, 8) */
+    int32_t sampling;              /* mppi_sampling */
+    int32_t cost_mode;             /* mppi_cost_mode */
+    float collision_weight;        /* weight of the collision indicator (MPPI_COST_INDICATOR) */
     int32_t reserved[2];           /* must be zero */
 } mppi_config;
 

@@ -11,13 +11,15 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdbasmppi.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 M, NMAX, PMAX = 2, 6, 16
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_BUSY = range(6)
 MODELS = {"quad6": 0, "quad5": 1, "car": 2}
 STATE_DIM = {"quad6": 6, "quad5": 5, "car": 4}
 NORMALISER = {"auto": 0, "on": 1, "off": 2}
 INIT_MODE = {"repeat": 0, "zero": 1}
+SAMPLING = {"nln": 0, "normal": 1}
+COST_MODE = {"dbas": 0, "indicator": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
 
 # Every entry point include/dbas_mppi.h declares.
@@ -55,7 +57,9 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("normaliser", ctypes.c_int32), ("init_mode", ctypes.c_int32),
         ("tile_samples", ctypes.c_int32), ("export_noise", ctypes.c_int32),
         ("adaptive_explore", ctypes.c_int32), ("explore_mu", ctypes.c_float),
-        ("sgf_half_window", ctypes.c_int32), ("sgf_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+        ("sgf_half_window", ctypes.c_int32), ("sgf_order", ctypes.c_int32),
+        ("sampling", ctypes.c_int32), ("cost_mode", ctypes.c_int32), ("collision_weight", ctypes.c_float),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

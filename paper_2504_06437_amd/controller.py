@@ -59,6 +59,9 @@ def make_config(params: dict) -> A.Config:
     c.explore_mu = float(params.get("explore_mu", 0.4))
     c.sgf_half_window = int(params.get("sgf_half_window", 0))
     c.sgf_order = int(params.get("sgf_order", 2))
+    c.sampling = A.SAMPLING[params.get("sampling", "nln")]
+    c.cost_mode = A.COST_MODE[params.get("cost_mode", "dbas")]
+    c.collision_weight = float(params.get("collision_weight", 1000.0))
     return c
 
 

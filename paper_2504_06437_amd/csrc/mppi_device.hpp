@@ -64,19 +64,26 @@ __device__ __forceinline__ float word_to_uniform(uint32_t r)
 
 // Normal x log-normal pair for inputs (0, 1) from one Philox block: Box-Muller
 // normals n from words (0, 1), z from words (2, 3);
-// du_c = sqrt(S_e) sigma_c n_c exp(mu_ln + sigma_ln z_c).
-__device__ __forceinline__ float2 nln_pair(uint4 r, float scale0, float scale1, float mu_ln, float sigma_ln)
+// du_c = sqrt(S_e) sigma_c n_c exp(mu_ln + sigma_ln z_c), or with `normal`
+// (Vanilla MPPI's law) the normal part sqrt(S_e) sigma_c n_c alone.
+__device__ __forceinline__ float2 nln_pair(uint4 r, float scale0, float scale1, float mu_ln, float sigma_ln,
+                                           bool normal)
 {
     const float u0 = word_to_uniform(r.x), u1 = word_to_uniform(r.y);
-    const float u2 = word_to_uniform(r.z), u3 = word_to_uniform(r.w);
     const float rn = sqrtf(-2.0f * logf(u0));
-    const float rz = sqrtf(-2.0f * logf(u2));
-    float sn, cn, sz, cz;
+    float sn, cn;
     sincospif(2.0f * u1, &sn, &cn);
-    sincospif(2.0f * u3, &sz, &cz);
     float2 o;
-    o.x = scale0 * (rn * cn) * expf(fmaf(sigma_ln, rz * cz, mu_ln));
-    o.y = scale1 * (rn * sn) * expf(fmaf(sigma_ln, rz * sz, mu_ln));
+    o.x = scale0 * (rn * cn);
+    o.y = scale1 * (rn * sn);
+    if (!normal) {
+        const float u2 = word_to_uniform(r.z), u3 = word_to_uniform(r.w);
+        const float rz = sqrtf(-2.0f * logf(u2));
+        float sz, cz;
+        sincospif(2.0f * u3, &sz, &cz);
+        o.x *= expf(fmaf(sigma_ln, rz * cz, mu_ln));
+        o.y *= expf(fmaf(sigma_ln, rz * sz, mu_ln));
+    }
     return o;
 }
 
@@ -601,6 +608,51 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
     return acc;
 }
 
+// The comparison controllers' constraint test of one pose (Sec. IV-A's
+// weighted indicator): lane sp of a group of js = 2^lg lanes returns the
+// smallest h of every shape point against obstacles sp, sp + js, ... and, with
+// a costmap, of shape points sp, sp + js, ... on the map (+inf when it has
+// none); the group's minimum decides whether the pose violates a constraint
+// (h < 0).  General form h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2, as the
+// runtime-P barrier takes it.
+__device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
+                                                const float* sb2, const float* ss, float4 pose, int sp, int lg,
+                                                bool with_map, float inv_res, float offx, float offy)
+{
+    constexpr int PM = MPPI_PMAX;
+    const float cs = pose.z, sn = pose.w;
+    const int J = p.J, js = 1 << lg;
+    float lo = INFINITY, lo2 = INFINITY;
+    float tx[PM], ty[PM];       // 2 d_i
+#pragma unroll
+    for (int i = 0; i < PM; ++i) {
+        tx[i] = fmaf(sa2[i], cs, -sb2[i] * sn);
+        ty[i] = fmaf(sa2[i], sn, sb2[i] * cs);
+    }
+    for (int j = sp; j < J; j += js) {
+        const float4 o = L.obs[j];
+        const float ex = pose.x - o.x, ey = pose.y - o.y;
+        const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
+#pragma unroll
+        for (int i = 0; i < PM; i += 2) {
+            if (i < P) lo = fminf(lo, fmaf(ex, tx[i], fmaf(ey, ty[i], ee + ss[i])));
+            if (i + 1 < P) lo2 = fminf(lo2, fmaf(ex, tx[i + 1], fmaf(ey, ty[i + 1], ee + ss[i + 1])));
+        }
+    }
+    lo = fminf(lo, lo2);
+    if (with_map) {
+#pragma unroll
+        for (int i = 0; i < PM; ++i) {
+            if (i < P && (i & (js - 1)) == sp) {
+                const float px = pose.x + 0.5f * tx[i];
+                const float py = pose.y + 0.5f * ty[i];
+                lo = fminf(lo, sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)));
+            }
+        }
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // One tile of S samples: rollout and the tile's softmax partials.
 // PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX; the
@@ -623,9 +675,10 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
 // shuffles.
 // Inputs, poses and barrier values are double-buffered by chunk parity.
 // ---------------------------------------------------------------------------
-template <int MODEL, int S, int PT, bool SC>
+template <int MODEL, int S, int PT, bool SC, bool IND>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
+    static_assert(!IND || PT == 0, "the indicator runs on the runtime-P tile");
     constexpr int NS = Model<MODEL>::NS;
     constexpr int PM = PT ? PT : MPPI_PMAX;
     constexpr int DW = (S + kWave - 1) / kWave;     // waves that own samples
@@ -703,6 +756,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 
     const float sqS = sqrtf(S_e);
     const float scale0 = sqS * p.sigma[0], scale1 = sqS * p.sigma[1];
+    const bool normal_law = p.sampling == MPPI_SAMPLE_NORMAL;
     const float cw0 = p.sigma[0] > 0.0f ? p.gamma_u / (S_e * p.sigma[0] * p.sigma[0]) : 0.0f;
     const float cw1 = p.sigma[1] > 0.0f ? p.gamma_u / (S_e * p.sigma[1] * p.sigma[1]) : 0.0f;
     const uint32_t c_lo = (uint32_t)ctr, c_hi = (uint32_t)(ctr >> 32);
@@ -746,7 +800,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         uint32_t k0 = __builtin_amdgcn_readfirstlane(p.seed_lo), k1 = __builtin_amdgcn_readfirstlane(p.seed_hi);
         asm volatile("" : "+s"(k0), "+s"(k1));
         const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), k0, k1);
-        return nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln);
+        return nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln, normal_law);
     };
 
     // inputs of every (step, sample) of chunk c, over threads [first, block)
@@ -794,7 +848,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    // barrier-state recursion over chunk c (owner lanes) and its cost
+    // barrier-state recursion over chunk c (owner lanes) and its cost; with
+    // the indicator, the weighted count of its steps that violate a
+    // constraint (the pool left each step's smallest h in bval)
     auto beta_chunk = [&](int c) __attribute__((always_inline)) {
         const int n = chunk_len(c);
         const float* bv = L.bval + (c & 1) * L.cs;
@@ -802,8 +858,12 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         for (int tt = 0; tt < n; ++tt) {
             const float b = nb;
             if (tt + 1 < n) nb = bv[(tt + 1) * S + tid];
-            beta = fmaf(p.gamma_b, beta, b);
-            two_sum_acc(S_hi, S_lo, p.r_b * beta);
+            if constexpr (IND) {
+                if (b < 0.0f) two_sum_acc(S_hi, S_lo, p.collision_weight);
+            } else {
+                beta = fmaf(p.gamma_b, beta, b);
+                two_sum_acc(S_hi, S_lo, p.r_b * beta);
+            }
         }
     };
 
@@ -858,11 +918,17 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         auto unit = [&](int u) __attribute__((always_inline)) {
             const int g = u * kWave + lane;
             const int item = g >> lg, sp = g & (nsp - 1);
-            float part = 0.0f;
-            if (item < items)
-                part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res,
-                                                     offx, offy);
-            for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
+            float part = IND ? INFINITY : 0.0f;
+            if constexpr (IND) {
+                if (item < items)
+                    part = clearance_pose(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res, offx, offy);
+                for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
+            } else {
+                if (item < items)
+                    part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res,
+                                                         offx, offy);
+                for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
+            }
             if (sp == 0 && item < items) bv[item] = part;
         };
         if constexpr (SC) {
@@ -889,7 +955,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // B(h(x_d)), x_d = x_ref[T]; the block reduction's barriers then order
     // both before stage 0.
     if (tid >= kRollBlock / 2) inputs_chunk(0, kRollBlock / 2);
-    {
+    if constexpr (IND) {
+        lds_barrier();                      // no barrier state: beta_0 = beta_d = 0
+    } else {
         const float2 b0d = block_sum_f2<kRollWaves>(
             fused_barrier_share2<PM>(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1],
                                      L.ref[T * NS + 2], inv_res, offx, offy),
@@ -1128,7 +1196,7 @@ __device__ __forceinline__ void touch_kernargs()
     asm volatile("" ::"s"(t));
 }
 
-template <int MODEL, int S, int PT>
+template <int MODEL, int S, int PT, bool IND>
 __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1144,15 +1212,16 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0[i];
     }
     xs.parity = a.parity;
-    rollout_tile<MODEL, S, PT, true>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
+    rollout_tile<MODEL, S, PT, true, IND>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
 
 template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD && p.shape_kind != kShapeGeneral) rollout_tile<MODEL, S, PD, false>(p, tile, xs, smem);
-    else rollout_tile<MODEL, S, 0, false>(p, tile, xs, smem);
+    if (p.cost_mode == MPPI_COST_INDICATOR) rollout_tile<MODEL, S, 0, false, true>(p, tile, xs, smem);
+    else if (p.P == PD && p.shape_kind != kShapeGeneral) rollout_tile<MODEL, S, PD, false, false>(p, tile, xs, smem);
+    else rollout_tile<MODEL, S, 0, false, false>(p, tile, xs, smem);
 }
 
 template <int MODEL>
@@ -1207,8 +1276,12 @@ template <int MODEL, int S>
 hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.P == PD && p.shape_kind != kShapeGeneral) hipLaunchKernelGGL((k_rollout<MODEL, S, PD>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
-    else hipLaunchKernelGGL((k_rollout<MODEL, S, 0>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    if (p.cost_mode == MPPI_COST_INDICATOR)
+        hipLaunchKernelGGL((k_rollout<MODEL, S, 0, true>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    else if (p.P == PD && p.shape_kind != kShapeGeneral)
+        hipLaunchKernelGGL((k_rollout<MODEL, S, PD, false>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    else
+        hipLaunchKernelGGL((k_rollout<MODEL, S, 0, false>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
     return hipGetLastError();
 }
 

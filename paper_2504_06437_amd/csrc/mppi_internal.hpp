@@ -63,6 +63,9 @@ struct DevParams {
     int32_t adaptive;        // 1: S_e follows the barrier cost of U*
     float explore_mu;
     int32_t sgf_m;           // Savitzky-Golay half window (0: no smoothing)
+    int32_t sampling;        // MPPI_SAMPLE_NLN or MPPI_SAMPLE_NORMAL (the normal part alone)
+    int32_t cost_mode;       // MPPI_COST_DBAS or MPPI_COST_INDICATOR (no barrier state)
+    float collision_weight;  // weight of the collision indicator
     int32_t shape_kind;      // ShapeForm: the layout form the model's fixed-P tile may use
     double beta_d_weight;    // R_B sum_{t=1..T} c_t / beta_d, the common barrier-state cost per unit of beta_d
     const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window

@@ -162,6 +162,9 @@ extern "C" int mppi_config_default(int32_t model, int32_t K, int32_t T, mppi_con
     c->tile_samples = 0;
     c->explore_mu = 0.4f;
     c->sgf_order = 2;
+    c->sampling = MPPI_SAMPLE_NLN;
+    c->cost_mode = MPPI_COST_DBAS;
+    c->collision_weight = 1000.0f;
     const int n = state_dim(model);
     for (int a = 0; a < n; ++a) c->Q[a] = a < 2 ? 1.0f : 0.1f;
     for (int a = 0; a < n; ++a) c->Qf[a] = 10.0f * c->Q[a];
@@ -240,6 +243,11 @@ std::string validate_config(const mppi_config* c)
         if (c->sgf_order < 0 || c->sgf_order > 2 * c->sgf_half_window || c->sgf_order > 8)
             return "sgf_order must lie in 0..min(2 sgf_half_window, 8)";
     }
+    if (c->sampling != MPPI_SAMPLE_NLN && c->sampling != MPPI_SAMPLE_NORMAL) return "unknown sampling law";
+    if (c->cost_mode != MPPI_COST_DBAS && c->cost_mode != MPPI_COST_INDICATOR) return "unknown cost mode";
+    if (!std::isfinite(c->collision_weight) || c->collision_weight < 0) return "collision_weight must be finite and >= 0";
+    if (c->cost_mode == MPPI_COST_INDICATOR && c->adaptive_explore)
+        return "adaptive exploration follows the barrier cost: it needs cost_mode MPPI_COST_DBAS";
     for (int i = 0; i < 2; ++i)
         if (c->reserved[i] != 0) return "reserved fields must be zero";
     return "";
@@ -400,6 +408,9 @@ void params_from_config(const mppi_config* cfg, DevParams& p)
     p.adaptive = cfg->adaptive_explore ? 1 : 0;
     p.explore_mu = cfg->explore_mu;
     p.sgf_m = cfg->sgf_half_window;
+    p.sampling = cfg->sampling;
+    p.cost_mode = cfg->cost_mode;
+    p.collision_weight = cfg->collision_weight;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
 }
@@ -837,7 +848,7 @@ extern "C" int mppi_get_step_info(mppi_t* h, mppi_step_info* info)
     info->tiles = h->p.tiles;
     info->S_e = st.S_e;
     info->cost_b = st.cost_b;
-    info->barrier_form = h->p.shape_kind;
+    info->barrier_form = h->p.cost_mode == MPPI_COST_INDICATOR ? 0 : h->p.shape_kind;
     info->noise_kept = tile_keeps_noise(h->p.J, h->cfg.T, h->p.n, h->p.spt) ? 1 : 0;
     return MPPI_OK;
 }

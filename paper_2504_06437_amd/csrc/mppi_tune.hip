@@ -1,5 +1,5 @@
 // Tile autotuner: samples per tile S for a (model, K, T, J, P, costmap,
-// smoothing) shape.  S sets the tile's reduction order, so one shape must get
+// smoothing, cost mode) shape.  S sets the tile's reduction order, so one shape must get
 // one S in every process for its results to repeat; the choice is looked up,
 // in order, in
 //   1. the process's own cache (every choice made or read so far),
@@ -28,7 +28,7 @@ using namespace dbas;
 
 namespace {
 
-using ShapeKey = std::tuple<int, int, int, int, int, int, int>;   // model K T J P map sgf_m
+using ShapeKey = std::tuple<int, int, int, int, int, int, int, int>;   // model K T J P map sgf_m cost_mode
 std::mutex g_tune_mu;
 std::map<ShapeKey, int> g_tune_cache;
 bool g_tables_read = false;
@@ -57,8 +57,8 @@ bool shape_ok(const ShapeKey& k, int S)
     return tile_samples_supported(S) && tile_fits(J, T, n, S, sgf) && (K + S - 1) / S <= kMaxTiles;
 }
 
-// Lines "model K T J P map sgf_m S"; '#' starts a comment line.  The first
-// entry of a shape wins.
+// Lines "model K T J P map sgf_m cost_mode S"; '#' starts a comment line.
+// The first entry of a shape wins.
 void read_table(const char* path)
 {
     if (!path || !*path) return;
@@ -67,11 +67,12 @@ void read_table(const char* path)
     char line[256];
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        int v[8];
-        if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]) != 8)
+        int v[9];
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7],
+                        &v[8]) != 9)
             continue;
-        const ShapeKey k{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
-        if (v[0] >= MPPI_QUAD6 && v[0] <= MPPI_CAR && shape_ok(k, v[7])) g_tune_cache.emplace(k, v[7]);
+        const ShapeKey k{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+        if (v[0] >= MPPI_QUAD6 && v[0] <= MPPI_CAR && shape_ok(k, v[8])) g_tune_cache.emplace(k, v[8]);
     }
     std::fclose(f);
 }
@@ -92,8 +93,8 @@ void append_cache(const ShapeKey& k, int S)
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                 std::get<4>(k), std::get<5>(k), std::get<6>(k), S);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                 std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), S);
     std::fclose(f);
 }
 
@@ -159,7 +160,7 @@ namespace dbas {
 int choose_tile_samples(mppi_ctrl* h)
 {
     const DevParams& p = h->p;
-    const ShapeKey key{p.model, p.K, p.T, p.J, p.P, p.sdf != nullptr ? 1 : 0, p.sgf_m};
+    const ShapeKey key{p.model, p.K, p.T, p.J, p.P, p.sdf != nullptr ? 1 : 0, p.sgf_m, p.cost_mode};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         read_tables_locked();

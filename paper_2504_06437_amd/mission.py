@@ -145,13 +145,14 @@ def summarize(results: list) -> dict:
             "timeouts": sum(1 for r in results if not r["reached"] and not r["collided"])}
 
 
-def run_mission(mission: int, runs: int = 10, first_seed: int = 0, device: int = 0) -> dict:
-    """`runs` experiments of one mission with the HIP controller."""
+def run_mission(mission: int, runs: int = 10, first_seed: int = 0, device: int = 0, controller: str = "dbas") -> dict:
+    """`runs` experiments of one mission with the HIP controller, as the
+    paper's controller ("dbas") or one of its baselines ("vanilla", "log")."""
     from .controller import Controller
     results = []
     for sd in range(first_seed, first_seed + runs):
         wl = layout(mission, sd)
-        c = Controller(wl["params"], device=device)
+        c = Controller(W.as_controller(wl["params"], controller), device=device)
         try:
             c.load_workload(wl)
             results.append(run(c, wl))
@@ -159,6 +160,7 @@ def run_mission(mission: int, runs: int = 10, first_seed: int = 0, device: int =
             c.close()
     out = summarize(results)
     out["mission"] = mission
+    out["controller"] = controller
     return out
 
 

@@ -53,12 +53,12 @@ def main(argv=None) -> int:
     with open(cache) as fh:
         for line in fh:
             f = line.split()
-            if len(f) == 8:
-                rows.setdefault(tuple(int(v) for v in f[:7]), int(f[7]))
+            if len(f) == 9:
+                rows.setdefault(tuple(int(v) for v in f[:8]), int(f[8]))
     os.unlink(cache)
     with open(args.out, "w") as fh:
         fh.write("# Rollout tile sizes measured on an MI355X by paper_2504_06437_amd/tune.py.\n")
-        fh.write("# model K T J P costmap sgf_half_window tile_samples\n")
+        fh.write("# model K T J P costmap sgf_half_window cost_mode tile_samples\n")
         for k in sorted(rows):
             fh.write(" ".join(str(v) for v in k) + f" {rows[k]}\n")
     print(f"[tune] {len(rows)} shapes -> {args.out}", flush=True)

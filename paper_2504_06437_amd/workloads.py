@@ -48,7 +48,7 @@ def base_params(model: str, K: int, T: int, seed: int = 0) -> dict:
         "model": model, "K": int(K), "T": int(T), "seed": int(seed),
         "mu_ln": 0.0, "sigma_ln": 0.3, "lambda": 1.0,
         "gamma_u": 2.0, "gamma_b": 0.5, "r_b": 0.1, "h_eps": 1e-4,
-        "init_mode": "repeat", "normaliser": "auto",
+        "init_mode": "repeat", "normaliser": "auto", "collision_weight": 1000.0,
         "mass": 0.5, "gravity": 9.81, "arm": 0.2, "inertia": 0.005, "wheelbase": 4.0,
     }
     if model == "quad6":
@@ -218,6 +218,26 @@ def tiny(model="quad6", K=4, T=3, J=2, seed=7) -> dict:
 
 def random_controls(rng, T, scale=0.3) -> np.ndarray:
     return (scale * rng.standard_normal((T, 2))).astype(np.float32)
+
+
+# The paper's controller and its two baselines (Sec. V, the mission table) as
+# settings of the same iteration: Vanilla MPPI samples the normal law and
+# pays a weighted collision indicator, Log-MPPI samples the normal x
+# log-normal mixture with the same indicator, DBaS-Log-MPPI samples the
+# mixture, carries the barrier state and adapts its exploration rate.
+CONTROLLERS = {
+    "vanilla": {"sampling": "normal", "cost_mode": "indicator", "adaptive_explore": False},
+    "log": {"sampling": "nln", "cost_mode": "indicator", "adaptive_explore": False},
+    "dbas": {"sampling": "nln", "cost_mode": "dbas", "adaptive_explore": True},
+}
+
+
+def as_controller(params: dict, name: str) -> dict:
+    """The parameters with the sampling law, collision cost and exploration
+    setting of controller `name` ("vanilla", "log" or "dbas")."""
+    out = dict(params)
+    out.update(CONTROLLERS[name])
+    return out
 
 
 NAMED = {"quad_small": quad_small, "car": car, "quad_large": quad_large}

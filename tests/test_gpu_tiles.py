@@ -48,7 +48,7 @@ def test_tile_choice_repeats_across_processes(tmp_path):
         outs.append((json.loads(r.stdout.strip().split("\n")[-1]), np.load(tmp_path / f"out{i}.npy")))
     lines = [ln.split() for ln in open(cache) if ln.strip()]
     assert len(lines) == 1 and lines[0][:4] == ["2", "3000", "37", "77"]
-    assert int(lines[0][7]) == outs[0][0]["tile_samples"] == outs[1][0]["tile_samples"]
+    assert int(lines[0][8]) == outs[0][0]["tile_samples"] == outs[1][0]["tile_samples"]
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
 
 
@@ -62,12 +62,12 @@ def test_shipped_table_sets_the_benchmark_tiles():
     for line in open(path):
         if not line.startswith("#") and line.strip():
             v = [int(x) for x in line.split()]
-            table[tuple(v[:7])] = v[7]
+            table[tuple(v[:8])] = v[8]
     from paper_2504_06437_amd.controller import Controller
     for wl in (W.car(), W.quad_large(), W.quad_small()):
         p = wl["params"]
         key = ({"quad6": 0, "quad5": 1, "car": 2}[p["model"]], p["K"], p["T"], len(wl["obstacles"]),
-               len(p["shape"]), 1 if wl.get("map") is not None else 0, 0)
+               len(p["shape"]), 1 if wl.get("map") is not None else 0, 0, 0)
         assert key in table
         c = Controller(p)
         c.load_workload(wl)

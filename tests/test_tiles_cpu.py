@@ -76,10 +76,10 @@ def test_shipped_tile_table_parses_and_fits(fit_exe):
     for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
-        model, K, T, J, P, cmap, m, S = (int(v) for v in line.split())
-        assert model in (0, 1, 2) and S in (16, 32, 64, 128, 256) and cmap in (0, 1)
-        assert (model, K, T, J, P, cmap, m) not in keys
-        keys.add((model, K, T, J, P, cmap, m))
+        model, K, T, J, P, cmap, m, mode, S = (int(v) for v in line.split())
+        assert model in (0, 1, 2) and S in (16, 32, 64, 128, 256) and cmap in (0, 1) and mode in (0, 1)
+        assert (model, K, T, J, P, cmap, m, mode) not in keys
+        keys.add((model, K, T, J, P, cmap, m, mode))
         rows.append((J, T, {0: 6, 1: 5, 2: 4}[model], S, m))
     assert rows
     assert all(f == 1 for f, _, _, _ in _query(fit_exe, rows))
