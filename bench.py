@@ -1,27 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of one DBaS-Log-MPPI iteration on one MI355X.
 
-A "step" is one iteration of the hot path: Philox normal x log-normal sampling,
-the barrier-state rollout with its cost, the min-shifted exponential weights
-and the weighted update with the warm-start shift, for the ground-vehicle
-workload (K=4096 samples, T=50, 100 circular obstacles, 8 shape points).
+A "step" is one iteration of the hot path -- Philox normal x log-normal
+sampling, the barrier-state rollout with its cost, the min-shifted
+exponential weights, the weighted update and the warm-start shift -- on the
+largest single-GPU workload: the planar quadrotor at scale (K = 16384 samples,
+T = 100 steps, 400 circular obstacles, 7 shape points, a 512 x 512
+signed-distance costmap, FP64 normaliser).
 
-Prints ONE JSON line.  `value` = rollout-steps/s (K*T per iteration) over the
-timed region: W untimed iterations, then `--steps` iterations issued back to
-back on the controller's stream with the states already in device memory,
+Prints ONE JSON line.  `value` = rollout-steps/s (K*T per iteration) over
+the timed region: W untimed iterations, then `--steps` iterations, each timed
+from its launch to u0 available on the host (the world, warm start and
+counter resident on the device; the state x0 passed with the launch),
 bracketed by device synchronisation.  Also reported:
-  * roofline of the rollout kernel (algorithmic FLOPs per launch / its mean
-    duration from HIP events recorded on its stream around every 32nd launch
-    of the timed region),
-  * p50/p99 control-step latency of the plain path (host state in, u0 out),
-  * the quadrotor at scale (K=16384, T=100, 400 obstacles + costmap),
+  * the roofline of the rollout kernel: algorithmic FLOPs per launch (7 per
+    (shape point, obstacle) pair, reciprocals counted apart) over its mean
+    duration from HIP events recorded on its stream around every launch of
+    the timed region, against the FP32 vector peak;
+  * the same iterations issued back to back from device-resident states
+    (pipelined);
+  * the ground vehicle (K=4096, T=50, 100 obstacles) with its own roofline,
+    and the small quadrotor (K=256, T=20, 10 obstacles) as a latency case;
   * the batched path: 64 mixed controllers in one graph-captured persistent
-    launch vs the same 64 stepped one after another through the plain path,
+    launch vs the same 64 stepped one after another through the plain path;
   * the served path: 256 robots sending Poisson 50 Hz request streams to the
-    continuous-batching server (p50/p99 arrival-to-response latency),
-  * the closed-loop missions (success, path error, average speed) on
-    synthetic layouts with the paper's mission settings,
-  * the FP64 CPU oracle timed on a bounded sample of the same workload.
+    continuous-batching server for 60 s (p50/p99 arrival-to-response);
+  * the paper's controller and its two baselines (Vanilla MPPI, Log-MPPI) at
+    the paper's mission sizes (M = 1024, N = 20), and the closed-loop
+    missions with each;
+  * the FP64 CPU oracle timed on a bounded sample of the headline workload,
+    on one core and on all the host cores it may use.
 """
 from __future__ import annotations
 
@@ -41,38 +49,55 @@ from paper_2504_06437_amd import workloads as W  # noqa: E402
 PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "rollout-steps/sec (K·T) and p50/p99 control-step latency, batched vs plain"
-# kernel durations come from HIP events around every PROFILE_EVERY-th
-# iteration of the timed loop (the events of one iteration add about 9 us to
-# it, so around every iteration they would cost a fifth of the step)
+# kernel durations of the shorter legs come from HIP events around every
+# PROFILE_EVERY-th iteration (the events of one iteration add a few
+# microseconds to it, a fifth of a vehicle step if taken around every one)
 PROFILE_EVERY = 32
 
+# Algorithmic work of one rollout step of one sample, by term: a
+# (shape point, obstacle) pair is dx, dy, two FMAs for h and the sum (7 FLOPs;
+# its reciprocal is counted apart); a shape point costs 2 FMAs on the
+# quadrotors' body axis and 4 on the vehicle's rectangle; a costmap point 15
+# FLOPs and one reciprocal; the dynamics and the stage, control and barrier
+# costs a fixed amount per model.
+PAIR_FLOPS = 7
+SHAPE_FLOPS = {"quad6": 4, "quad5": 4, "car": 8}
+DYNAMICS_FLOPS = {"quad6": 14, "quad5": 12, "car": 10}
+COST_FLOPS = {"quad6": 27, "quad5": 24, "car": 21}
+MAP_FLOPS = 15
 
-def rollout_flops_per_step(params: dict, J: int, with_map: bool) -> float:
-    """Algorithmic FP32 work of one (sample, step) of the rollout.
 
-    per obstacle pair: dx, dy (2), h = dx^2 + dy^2 - r^2 (2 FMA = 4),
-        B = 1/max(h, eps) (1), accumulate (1)                      -> 8
-    per shape point: rotate + translate (2 x (mul, FMA, add) = 8)    -> 8
-    per shape point with a costmap: 2 FMA coords (4), 3 lerps (9),
-        B (1), accumulate (1)                                      -> 15
-    per step, fixed: noise (2 x (2 FMA uniforms, log, sqrt, sincos pair,
-        mul, FMA + exp, 2 mul) = 34), saturation (4), dynamics (quad 20,
-        car 14), heading sincos (2), barrier state (2), stage cost
-        (4 n), control cost (6), compensated add (6)
-    """
+def rollout_flops_per_step(params: dict, J: int, with_map: bool) -> int:
     P = len(params["shape"])
-    n = W.MODEL_DIMS[params["model"]]
-    fixed = 34 + 4 + (14 if params["model"] == "car" else 20) + 2 + 2 + 4 * n + 6 + 6
-    return 8.0 * P * J + 8.0 * P + (15.0 * P if with_map else 0.0) + fixed
+    m = params["model"]
+    return (PAIR_FLOPS * P * J + SHAPE_FLOPS[m] * P + DYNAMICS_FLOPS[m] + COST_FLOPS[m]
+            + (MAP_FLOPS * P if with_map else 0))
+
+
+def rollout_rcp_per_step(params: dict, J: int, with_map: bool) -> int:
+    P = len(params["shape"])
+    return P * J + (P if with_map else 0)
 
 
 def percentile(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def make_controller(wl):
+def workload_name(wl) -> str:
+    p = wl["params"]
+    body = {"quad6": "quadrotor", "quad5": "quadrotor (5-state)", "car": "ground vehicle"}[p["model"]]
+    s = f"{body} K={p['K']} T={p['T']} J={len(wl['obstacles'])} P={len(p['shape'])}"
+    if wl.get("map") is not None:
+        n = wl["map"]["sdf"].shape[0]
+        s += f" + {n}x{n} costmap"
+    if p.get("normaliser") == "on":
+        s += ", fp64 normaliser"
+    return s
+
+
+def make_controller(wl, params=None):
     from paper_2504_06437_amd.controller import Controller
-    c = Controller(wl["params"])
+    c = Controller(params or wl["params"])
     c.load_workload(wl)
     return c
 
@@ -93,80 +118,125 @@ def closed_loop_states(c, wl, steps):
     return np.asarray(xs, dtype=np.float32), lat
 
 
-def bench_plain(wl, steps, warmup):
+def roofline(p, J, with_map, kernel_ms, launches, extra=None):
+    flops = p["K"] * p["T"] * rollout_flops_per_step(p, J, with_map)
+    rcp = p["K"] * p["T"] * rollout_rcp_per_step(p, J, with_map)
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": "rollout",
+           "kernel_ms_mean": kernel_ms, "flops_per_launch": flops, "rcp_per_launch": rcp,
+           "rcp_per_s": rcp / (kernel_ms * 1e-3), "launches_timed": launches}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def bench_leg(wl, steps, warmup, profile_every, pipelined_steps):
+    """One workload: `steps` synchronous iterations (launch to u0 on the host,
+    each timed) with HIP events on the controller's stream around the kernels
+    of every `profile_every`-th one, then `pipelined_steps` iterations issued
+    back to back from device-resident states."""
     from paper_2504_06437_amd import hip
     c = make_controller(wl)
     p = wl["params"]
     K, T = p["K"], p["T"]
-    n_states = 200                      # closed-loop states, cycled through by the timed loop
-    states, lat = closed_loop_states(c, wl, n_states)
-    lat = lat[min(20, len(lat) // 4):]
-    x_dev = hip.DeviceArray.from_numpy(states)
-    u_dev = hip.DeviceArray((n_states, 2))
-    hip.synchronize()
+    n_states = 200
+    states, _ = closed_loop_states(c, wl, n_states)
     for i in range(warmup):
-        c.step_async(x_dev.at(i % n_states), u_dev.at(i % n_states))
-    assert c.synchronize() == 0
-    c.profile(PROFILE_EVERY)
-    ev0, ev1 = hip.Event(), hip.Event()
+        c.step(states[i % n_states])
+    c.profile(profile_every)
+    lat = []
     hip.synchronize()
     t0 = time.perf_counter()
-    ev0.record(c.stream)
     for i in range(steps):
-        c.step_async(x_dev.at(i % n_states), u_dev.at(i % n_states))
-    ev1.record(c.stream)
+        t1 = time.perf_counter()
+        c.step(states[i % n_states])
+        lat.append(time.perf_counter() - t1)
     status = c.synchronize()
     hip.synchronize()
     wall = time.perf_counter() - t0
     prof = c.profile_read()
     c.profile(False)
-    info = c.info()
-    ev_ms = ev0.elapsed_ms(ev1)
-    c.close()
     assert status == 0, status
+    # pipelined: device-resident states, no host round trip per iteration
+    x_dev = hip.DeviceArray.from_numpy(states)
+    u_dev = hip.DeviceArray((n_states, 2))
+    for i in range(warmup):
+        c.step_async(x_dev.at(i % n_states), u_dev.at(i % n_states))
+    assert c.synchronize() == 0
+    hip.synchronize()
+    tp = time.perf_counter()
+    for i in range(pipelined_steps):
+        c.step_async(x_dev.at(i % n_states), u_dev.at(i % n_states))
+    assert c.synchronize() == 0
+    hip.synchronize()
+    wall_p = time.perf_counter() - tp
+    info = c.info()
+    c.close()
+    n_prof = max(prof["iterations"], 1)
     return {
-        "wall_s": wall, "event_ms": ev_ms, "rollout_steps_per_s": K * T * steps / wall,
-        "ms_per_step": 1e3 * wall / steps, "rollout_ms_mean": prof["rollout_ms"] / max(prof["iterations"], 1),
-        "update_ms_mean": prof["update_ms"] / max(prof["iterations"], 1), "profiled": prof["iterations"],
-        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99), "n": len(lat)},
-        "tile_samples": info["tile_samples"], "tiles": info["tiles"],
+        "workload": workload_name(wl), "wall_s": wall, "steps": steps,
+        "rollout_steps_per_s": K * T * steps / wall, "ms_per_step": 1e3 * wall / steps,
+        "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+        "rollout_steps_per_s_at_p50": K * T / percentile(lat, 50),
+        "rollout_ms_mean": prof["rollout_ms"] / n_prof, "update_ms_mean": prof["update_ms"] / n_prof,
+        "profiled": prof["iterations"],
+        "pipelined": {"steps": pipelined_steps, "ms_per_step": 1e3 * wall_p / pipelined_steps,
+                      "rollout_steps_per_s": K * T * pipelined_steps / wall_p},
+        "tile_samples": info["tile_samples"], "tiles": info["tiles"], "fp64_tiles": info["fp64_tiles"],
+        "noise_kept": info["noise_kept"], "barrier_form": info["barrier_form"],
     }
 
 
-def bench_at_scale(steps=20, warmup=3):
-    """The quadrotor at scale: K=16384, T=100, 400 obstacles + 512x512
-    costmap, FP64 normaliser.  Steps issued back to back from device-resident
-    states; rollout-kernel time from HIP events around every launch of this
-    short loop (events cost ~1% of an 0.8 ms kernel)."""
-    from paper_2504_06437_amd import hip
-    wl = W.quad_large()
-    p = wl["params"]
+def bench_latency(wl, steps=50, rounds=4):
+    """The small case: `rounds` receding-horizon runs of `steps` control steps
+    each, closed loop through the host plant; every step is a synchronous
+    iteration (host state in, u0 out)."""
     c = make_controller(wl)
-    x_dev = hip.DeviceArray.from_numpy(np.stack([wl["x0"]] * 4))
-    u_dev = hip.DeviceArray((4, 2))
-    for i in range(warmup):
-        c.step_async(x_dev.at(i % 4), u_dev.at(i % 4))
-    assert c.synchronize() == 0
+    lat = []
+    for _ in range(rounds):
+        c.set_controls(np.zeros((wl["params"]["T"], 2), dtype=np.float32))
+        _, l = closed_loop_states(c, wl, steps)
+        lat.extend(l[1:])
     c.profile(1)
-    hip.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        c.step_async(x_dev.at(i % 4), u_dev.at(i % 4))
-    status = c.synchronize()
-    wall = time.perf_counter() - t0
+    closed_loop_states(c, wl, steps)
     prof = c.profile_read()
-    info = c.info()
     c.close()
-    assert status == 0, status
-    J = len(wl["obstacles"])
-    kernel_ms = prof["rollout_ms"] / max(prof["iterations"], 1)
-    flops = p["K"] * p["T"] * rollout_flops_per_step(p, J, True)
-    achieved = flops / (kernel_ms * 1e-3) / 1e12
-    return {"workload": f"quadrotor K={p['K']} T={p['T']} J={J} P={len(p['shape'])} + 512x512 costmap",
-            "rollout_steps_per_s": p["K"] * p["T"] * steps / wall, "ms_per_step": 1e3 * wall / steps,
-            "rollout_kernel_ms_mean": kernel_ms, "update_kernel_ms_mean": prof["update_ms"] / max(prof["iterations"], 1),
-            "achieved_tflops": achieved, "frac_of_fp32_peak": achieved / PEAK_FP32_VECTOR_TFLOPS,
-            "tile_samples": info["tile_samples"], "fp64_tiles": info["fp64_tiles"], "steps": steps}
+    p = wl["params"]
+    n = max(prof["iterations"], 1)
+    return {"workload": workload_name(wl), "steps": len(lat), "p50_ms": 1e3 * percentile(lat, 50),
+            "p99_ms": 1e3 * percentile(lat, 99), "rollout_steps_per_s_at_p50": p["K"] * p["T"] / percentile(lat, 50),
+            "rollout_kernel_ms_mean": prof["rollout_ms"] / n, "update_kernel_ms_mean": prof["update_ms"] / n}
+
+
+def bench_controllers(runs_per=200):
+    """The paper's controller and its baselines at the mission sizes (M =
+    1024 samples, N = 20 steps): the same kernels in the three modes, on the
+    first quadrotor and vehicle mission layouts.  Synchronous step latency
+    and kernel times, to compare with the paper's finding of no significant
+    difference in processing time among the three."""
+    from paper_2504_06437_amd import mission
+    out = []
+    for m in (1, 2):
+        wl = mission.layout(m, 0)
+        for name in ("vanilla", "log", "dbas"):
+            c = make_controller(wl, W.as_controller(wl["params"], name))
+            x = wl["x0"]
+            for _ in range(20):
+                c.step(x)
+            lat = []
+            c.profile(1)
+            for _ in range(runs_per):
+                t0 = time.perf_counter()
+                c.step(x)
+                lat.append(time.perf_counter() - t0)
+            prof = c.profile_read()
+            c.close()
+            n = max(prof["iterations"], 1)
+            out.append({"mission": m, "controller": name, "workload": workload_name(wl),
+                        "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                        "rollout_kernel_us": 1e3 * prof["rollout_ms"] / n, "update_kernel_us": 1e3 * prof["update_ms"] / n})
+    return out
 
 
 def bench_batched(n_ctrl=64, steps=30, seed=3):
@@ -175,6 +245,8 @@ def bench_batched(n_ctrl=64, steps=30, seed=3):
     wls = W.batch(n_ctrl, seed)
     ctrls = [make_controller(wl) for wl in wls]
     total = sum(wl["params"]["K"] * wl["params"]["T"] for wl in wls)
+    flops = sum(wl["params"]["K"] * wl["params"]["T"] * rollout_flops_per_step(wl["params"], len(wl["obstacles"]), False)
+                for wl in wls)
     x0s = [wl["x0"] for wl in wls]
     # plain path, sequential: every controller synchronously, one after another
     for c, wl in zip(ctrls, wls):
@@ -198,15 +270,16 @@ def bench_batched(n_ctrl=64, steps=30, seed=3):
     for c in ctrls:
         c.close()
     return {
-        "controllers": n_ctrl, "rollout_steps_per_iteration": int(total),
+        "controllers": n_ctrl, "rollout_steps_per_iteration": int(total), "flops_per_iteration": flops,
         "batched": {"rollout_steps_per_s": total / percentile(lat, 50), "p50_ms": 1e3 * percentile(lat, 50),
-                    "p99_ms": 1e3 * percentile(lat, 99), "n": len(lat)},
+                    "p99_ms": 1e3 * percentile(lat, 99), "n": len(lat),
+                    "tflops_at_p50": flops / percentile(lat, 50) / 1e12},
         "plain_sequential": {"rollout_steps_per_s": total / percentile(seq, 50), "p50_ms": 1e3 * percentile(seq, 50),
                              "p99_ms": 1e3 * percentile(seq, 99), "n": len(seq)},
     }
 
 
-def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 << 20, streams=3):
+def bench_served(seconds=60.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 << 20, streams=3):
     """Poisson request streams from `n_robots` robots (sizes as the mixed
     batch) at `rate_hz` each, closed loop through the host plant, served by the
     continuous-batching server.  Latency = completion - scheduled arrival, so
@@ -239,8 +312,12 @@ def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 <<
     lat, statuses, served_steps, lag_max = [], [], 0, 0.0
     t0 = srv.now() + 0.05
     i, t_end = 0, t0
+    next_note = 10.0
     while i < len(arrivals) or waiting:
         now = srv.now()
+        if now - t0 >= next_note:
+            print(f"[bench] served: {next_note:.0f} s, {len(lat)} responses", file=sys.stderr, flush=True)
+            next_note += 10.0
         if i < len(arrivals) and now >= t0 + arrivals[i][0]:
             t, r = arrivals[i]
             i += 1
@@ -281,32 +358,74 @@ def bench_served(seconds=10.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 <<
     }
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """The FP64 oracle, single-threaded, on whole iterations of the same workload."""
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def host_threads() -> int:
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(n, avail) if n > 0 else avail)
+
+
+def cpu_baseline(wl, single_s=12.0, multi_s=8.0):
+    """The FP64 oracle (plain C, gcc -O2, threaded over samples when asked) on
+    whole iterations of the same workload: first on one core, then on every
+    core this process may use.  The all-core figure is `value`."""
     import oracle
     p = wl["params"]
     world = oracle.World.from_workload(wl)
-    U = wl["U0"].astype(np.float64)
-    iters, t0 = 0, time.perf_counter()
-    while True:
-        r = oracle.step(p, world, wl["x0"], U, wl["x_ref"], 1.0, iters)
-        U = r["Unext"]
-        iters += 1
-        el = time.perf_counter() - t0
-        if (el >= budget_s and iters >= 2) or el >= 3 * budget_s:
-            break
-    return {"value": p["K"] * p["T"] * iters / el, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} full iterations of the same workload (K={p['K']}, T={p['T']}, J={len(wl['obstacles'])}), "
-                      f"FP64, single thread, {el:.1f} s"}
+
+    def run(threads, budget):
+        oracle.set_threads(threads)
+        U = wl["U0"].astype(np.float64)
+        iters, t0 = 0, time.perf_counter()
+        while True:
+            r = oracle.step(p, world, wl["x0"], U, wl["x_ref"], 1.0, iters, diagnostics=False)
+            U = r["Unext"]
+            iters += 1
+            el = time.perf_counter() - t0
+            if el >= budget or iters >= 50:
+                break
+        return iters, el
+
+    it1, el1 = run(1, single_s)
+    nt = host_threads()
+    itn, eln = run(nt, multi_s)
+    oracle.set_threads(1)
+    kt = p["K"] * p["T"]
+    return {"value": kt * itn / eln, "unit": "rollout-steps/s", "cores": nt, "kind": "oracle",
+            "sample": f"{itn} full iterations of the headline workload ({workload_name(wl)}), FP64, "
+                      f"{nt} threads over samples, {eln:.1f} s",
+            "single_core": {"value": kt * it1 / el1, "cores": 1, "iterations": it1, "seconds": el1},
+            "cpu_model": host_cpu(), "host_cpus_available": host_threads()}
+
+
+def _kernel_sources():
+    csrc = os.path.join(ROOT, "paper_2504_06437_amd", "csrc")
+    names = ["mppi_device.hpp", "mppi_kernels.hip"] + sorted(
+        f for f in os.listdir(csrc) if f.startswith("mppi_rollout_") and f.endswith(".hip"))
+    return "\n".join(open(os.path.join(csrc, n)).read() for n in names)
 
 
 def _kernel_digest(text: str | None = None) -> str:
-    """SHA-256 (16 hex digits) of the kernel source's code: comments removed
+    """SHA-256 (16 hex digits) of the kernels' source code: comments removed
     and whitespace collapsed, so that a comment edit keeps the records."""
     import hashlib
     import re
     if text is None:
-        text = open(os.path.join(ROOT, "paper_2504_06437_amd", "csrc", "mppi_kernels.hip")).read()
+        text = _kernel_sources()
     code = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     code = re.sub(r"//[^\n]*", " ", code)
     code = " ".join(code.split())
@@ -444,18 +563,24 @@ def update_roofline(p: dict, r: dict) -> dict:
             "note": f"latency-bound: {b / 1e6:.2f} MB over {(2 * p['T'] + 3) // 4} workgroups"}
 
 
+WORKLOADS = {"c2": W.quad_large, "c1": W.car, "c0": W.quad_small}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1024)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
+                    help="headline workload (c2: the quadrotor at scale; c1, c0 for profiling runs)")
+    ap.add_argument("--only-headline", action="store_true", help="skip every extra leg")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-missions", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the vehicle, small-quadrotor and controller legs")
     ap.add_argument("--mission-runs", type=int, default=10)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("SQ1", "SQ2"),
@@ -465,17 +590,11 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     args = ap.parse_args()
     if args.summarize_counters:
-        wl = W.car()
-        p = wl["params"]
-        workload = f"ground vehicle K={p['K']} T={p['T']} J={len(wl['obstacles'])} P={len(p['shape'])}"
-        print(json.dumps(summarize_counters(*args.summarize_counters, workload,
+        print(json.dumps(summarize_counters(*args.summarize_counters, workload_name(WORKLOADS[args.workload]()),
                                             os.path.join(ROOT, "profiles", "counters.json")), indent=1))
         return
     if args.summarize_traffic:
-        wl = W.car()
-        p = wl["params"]
-        workload = f"ground vehicle K={p['K']} T={p['T']} J={len(wl['obstacles'])} P={len(p['shape'])}"
-        r = summarize_traffic(*args.summarize_traffic, args.copy_bytes, workload,
+        r = summarize_traffic(*args.summarize_traffic, args.copy_bytes, workload_name(WORKLOADS[args.workload]()),
                               os.path.join(ROOT, "profiles", "traffic.json"))
         print(json.dumps(r, indent=1))
         return
@@ -483,39 +602,54 @@ def main():
         print(json.dumps(copy_calibration(args.copy_calibration)), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
-              "is described but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): every run here uses one GPU; "
+              "the multi-GPU design is described but not built.", file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.no_batched = args.no_cpu = args.no_served = args.no_missions = args.no_legs = True
 
-    wl = W.car()
+    wl = WORKLOADS[args.workload]()
     p = wl["params"]
     J = len(wl["obstacles"])
-    print(f"[bench] plain path: car K={p['K']} T={p['T']} J={J}", file=sys.stderr, flush=True)
-    r = bench_plain(wl, args.steps, args.warmup)
-    flops = p["K"] * p["T"] * rollout_flops_per_step(p, J, False)
-    achieved = flops / (r["rollout_ms_mean"] * 1e-3) / 1e12
-    workload = f"ground vehicle K={p['K']} T={p['T']} J={J} P={len(p['shape'])}"
+    with_map = wl.get("map") is not None
+    name = workload_name(wl)
+    print(f"[bench] headline: {name}, {args.steps} timed steps", file=sys.stderr, flush=True)
+    # events around every launch of the headline's timed region (at this size
+    # they cost about one per cent of a step)
+    r = bench_leg(wl, args.steps, args.warmup, 1 if args.workload == "c2" else PROFILE_EVERY,
+                  pipelined_steps=max(args.steps, 100))
+    rl = roofline(p, J, with_map, r["rollout_ms_mean"], r["profiled"],
+                  {"update_kernel_ms_mean": r["update_ms_mean"], "timed_every": 1 if args.workload == "c2" else PROFILE_EVERY})
+    rl["traffic"] = load_traffic("rollout", name)
+    rl["valu"] = load_counters("rollout", name)
     out = {
         "metric": METRIC, "value": r["rollout_steps_per_s"], "unit": "rollout-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": workload, "K": p["K"], "T": p["T"], "obstacles": J, "shape_points": len(p["shape"]),
-                   "tile_samples": r["tile_samples"], "tiles": r["tiles"], "normaliser": "fp32 (fp64 when |rho|/lambda>=1024)"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": load_traffic("rollout", workload),
-                     "kernel": "rollout", "kernel_ms_mean": r["rollout_ms_mean"],
-                     "update_kernel_ms_mean": r["update_ms_mean"], "flops_per_launch": flops,
-                     "launches_timed": r["profiled"], "timed_every": PROFILE_EVERY,
-                     "valu": load_counters("rollout", workload)},
+        "config": {"workload": name, "K": p["K"], "T": p["T"], "obstacles": J, "shape_points": len(p["shape"]),
+                   "costmap": list(wl["map"]["sdf"].shape) if with_map else None,
+                   "normaliser": p.get("normaliser", "auto"), "tile_samples": r["tile_samples"], "tiles": r["tiles"],
+                   "timed": "each step from its launch to u0 on the host; world, warm start and counter in HBM"},
+        "roofline": rl,
         "update_roofline": update_roofline(p, r),
-        "latency_ms": {"plain_p50": r["latency_ms"]["p50"], "plain_p99": r["latency_ms"]["p99"],
-                       "n": r["latency_ms"]["n"], "note": "host state in, u0 out (PCIe-inclusive)"},
-        "timing": {"wall_s": r["wall_s"], "event_ms": r["event_ms"]},
+        "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"], "n": args.steps,
+                       "rollout_steps_per_s_at_p50": r["rollout_steps_per_s_at_p50"]},
+        "pipelined": r["pipelined"],
+        "timing": {"wall_s": r["wall_s"], "fp64_tiles": r["fp64_tiles"], "noise_kept": r["noise_kept"],
+                   "barrier_form": r["barrier_form"]},
     }
-    if not args.no_scale:
-        print("[bench] quadrotor at scale", file=sys.stderr, flush=True)
-        out["at_scale"] = bench_at_scale()
+    if not args.no_legs:
+        print("[bench] vehicle leg", file=sys.stderr, flush=True)
+        wc = W.car()
+        rc = bench_leg(wc, 1024, 20, PROFILE_EVERY, pipelined_steps=1024)
+        rc["roofline"] = roofline(wc["params"], len(wc["obstacles"]), False, rc["rollout_ms_mean"], rc["profiled"],
+                                  {"timed_every": PROFILE_EVERY})
+        rc["update_roofline"] = update_roofline(wc["params"], rc)
+        out["vehicle"] = rc
+        print("[bench] small quadrotor latency leg", file=sys.stderr, flush=True)
+        out["small"] = bench_latency(W.quad_small())
+        print("[bench] controllers at the mission sizes", file=sys.stderr, flush=True)
+        out["controllers"] = bench_controllers()
     if not args.no_batched:
         print("[bench] batched path: 64 mixed controllers", file=sys.stderr, flush=True)
         out["batched"] = bench_batched()
@@ -524,9 +658,11 @@ def main():
         out["served"] = bench_served(args.serve_seconds)
     if not args.no_missions:
         from paper_2504_06437_amd import mission
-        print(f"[bench] missions: {args.mission_runs} closed-loop runs each", file=sys.stderr, flush=True)
+        print(f"[bench] missions: {args.mission_runs} closed-loop runs each, three controllers", file=sys.stderr,
+              flush=True)
         out["missions"] = {"note": "synthetic layouts with the paper's mission settings; not its layouts",
-                           "results": [mission.run_mission(m, args.mission_runs) for m in (1, 2, 3)]}
+                           "results": [mission.run_mission(m, args.mission_runs, controller=c)
+                                       for c in ("dbas", "log", "vanilla") for m in (1, 2, 3)]}
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -400,10 +400,13 @@ def sgf(y, half_window: int, order: int) -> np.ndarray:
     return out
 
 
-def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int) -> dict:
+def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int, diagnostics: bool = True) -> dict:
     """One full iteration; returns every intermediate as FP64 arrays.  With
     params["sgf_half_window"] = m > 0 the weighted increment is smoothed by
-    sgf(., m, params["sgf_order"]) before it is added to U (Algorithm 1)."""
+    sgf(., m, params["sgf_order"]) before it is added to U (Algorithm 1).
+    diagnostics=False skips the per-sample clearance and sensitivity (the
+    tolerance diagnostics; "clear" and "sens" are then None): the iteration
+    alone, as the CPU baseline times it."""
     cfg = make_cfg(params)
     K, T = cfg.K, cfg.T
     x0, U, x_ref = _f64(x0), _f64(U), _f64(x_ref)
@@ -413,12 +416,14 @@ def step(params: dict, world: World, x0, U, x_ref, S_e: float, counter: int) -> 
     Ustar = np.zeros((T, 2))
     Unext = np.zeros((T, 2))
     u0 = np.zeros(2)
-    clear = np.zeros(K)
-    sens = np.zeros(K)
+    clear = np.zeros(K) if diagnostics else None
+    sens = np.zeros(K) if diagnostics else None
+    null = ctypes.POINTER(ctypes.c_double)()
     sc = [ctypes.c_double() for _ in range(4)]
     st = lib().orc_step(ctypes.byref(cfg), ctypes.byref(world.s), _dp(x0), _dp(U), _dp(x_ref),
                         float(S_e), int(counter), _dp(du), _dp(S), _dp(w), _dp(Ustar), _dp(Unext),
-                        _dp(u0), *[ctypes.byref(s) for s in sc], _dp(clear), _dp(sens))
+                        _dp(u0), *[ctypes.byref(s) for s in sc], _dp(clear) if diagnostics else null,
+                        _dp(sens) if diagnostics else null)
     m = int(params.get("sgf_half_window", 0))
     if m > 0 and st == OK:
         inc = np.einsum("k,ktc->tc", w, du)

@@ -101,16 +101,30 @@ def test_committed_records_match_the_kernel_source():
             pytest.skip(f"profiles/{name} predates the kernel source; the bench reports null until re-profiled")
 
 
-def test_vehicle_workload_flops():
-    """8 FLOPs a pair (P x J pairs), 8 a shape point and, for the vehicle, 84
-    fixed per rollout step (noise 34, saturation 4, dynamics 14, heading 2,
-    barrier state 2, stage cost 16, control cost 6, compensated add 6):
-    6 548 per step and 1.341 GFLOP per launch at K=4096, T=50, J=100."""
-    wl = W.car()
-    p = wl["params"]
-    per_step = bench.rollout_flops_per_step(p, len(wl["obstacles"]), False)
-    assert per_step == 6548
-    assert p["K"] * p["T"] * per_step == 1341030400
+def test_algorithmic_flops_follow_the_per_term_table():
+    """7 FLOPs a (shape point, obstacle) pair, reciprocals apart; 2 FMAs a
+    shape point on the quadrotor's axis, 4 on the vehicle's rectangle; 15
+    FLOPs and a reciprocal a costmap point; dynamics 14 (quadrotor) or 10
+    (vehicle); stage, control and barrier costs 27 or 21.  Per rollout step:
+    559 (small quadrotor), 5 695 (vehicle), 19 774 (quadrotor at scale), and
+    3.24e10 FLOPs with 4.6e9 reciprocals per launch at scale."""
+    for wl, flops, rcp in ((W.quad_small(), 559, 70), (W.car(), 5695, 800),
+                           (W.quad_large(cells=16), 19774, 2807)):
+        p = wl["params"]
+        m = wl.get("map") is not None
+        assert bench.rollout_flops_per_step(p, len(wl["obstacles"]), m) == flops
+        assert bench.rollout_rcp_per_step(p, len(wl["obstacles"]), m) == rcp
+    p = W.quad_large(cells=16)["params"]
+    assert p["K"] * p["T"] * 19774 == pytest.approx(3.24e10, rel=1e-3)
+    r = bench.roofline(p, 400, True, kernel_ms=0.5, launches=10)
+    assert r["achieved"] == pytest.approx(p["K"] * p["T"] * 19774 / 0.5e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    assert r["rcp_per_launch"] == p["K"] * p["T"] * 2807
+
+
+def test_workload_names():
+    assert bench.workload_name(W.car()) == WORKLOAD
+    assert bench.workload_name(W.quad_large(cells=16)).startswith("quadrotor K=16384 T=100 J=400 P=7 + 16x16 costmap")
 
 
 def test_more_than_one_gpu_is_refused():
