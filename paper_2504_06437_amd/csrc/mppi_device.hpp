@@ -267,6 +267,16 @@ __device__ __forceinline__ void reciprocal_sum(const float* h, float& acc, float
     }
 }
 
+// sum_i 1/h_i of N clamped values as a value (the clamped form of the layout
+// bodies' obstacles that leave the pair-fraction form).
+template <int N>
+__device__ __forceinline__ float reciprocal_total(const float* h)
+{
+    float a = 0.0f, b = 0.0f;
+    reciprocal_sum<N>(h, a, b);
+    return a + b;
+}
+
 // Bilinear costmap sample between cell centres, clamped to the edge cells.
 // (gx, gy) are continuous cell coordinates; any float input stays in bounds.
 __device__ __forceinline__ float sdf_sample(const float* __restrict__ sdf, int W, int H, float gx, float gy)
@@ -529,42 +539,93 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         }
         if (sp < rem) body(ob[0]);
     };
+    // Pair fractions (the layout forms' fast path).  Two points whose h are
+    // c + d and c - d give 1/(c+d) + 1/(c-d) = 2c/(c^2 - d^2); the bodies of
+    // Sec. V split into such pairs (the vehicle's four, the quadrotor's three
+    // mirrored ones plus its middle point), and their fractions meet in one:
+    // one reciprocal per obstacle, no clamp.  It holds when every h of the
+    // obstacle is at least gmin = max(h_eps, 1e-4) -- then B(h) = 1/h, and
+    // every h lies in [gmin, 2c] -- and c is at most the form's cap, so the
+    // products of all the h stay inside the FP32 range.  Any other obstacle
+    // takes the clamped per-point form.  `half` sums c/q, half of each
+    // fraction.
+    const float gmin = fmaxf(eps, 1e-4f);
+    float half = 0.0f;
     if constexpr (PT != 0 && MODEL == MPPI_CAR) {
         static_assert(PT == 8, "vehicle layout: 8 points");
         // point 0 is (a, b); o.z = -r^2 + a^2 + b^2, so C = |e|^2 - r^2 + a^2 +
         // b^2 takes two operations, and with P = 2a e.u, Q = 2b e.v the
         // corners are (C +- P) +- Q, the side midpoints C +- P - b^2 and
-        // C - a^2 +- Q: 19 operations for the 8 pairs
+        // C - a^2 +- Q.  Pairs: (C+P) +- Q, (C-P) +- Q, (C-b^2) +- P and
+        // (C-a^2) +- Q; the smallest h is C - |P| - |Q| (a corner),
+        // C - b^2 - |P| or C - a^2 - |Q|, the largest at most 2C.
+        // Cap: C <= 2e4, so 8 values of h <= 4e4 multiply below 7e36.
+        constexpr float kCap = 2.0e4f;
         const float AA = ss[4], BB = ss[6];
         const float cu = sa2[0] * cs, su = sa2[0] * sn, cv = sb2[0] * cs, sv = sb2[0] * sn;
         run([&](const float4 o) __attribute__((always_inline)) {
             const float ex = pose.x - o.x, ey = pose.y - o.y;
             const float C = fmaf(ex, ex, fmaf(ey, ey, o.z));
             const float Pu = fmaf(ex, cu, ey * su), Qv = fmaf(ey, cv, -ex * sv);
-            const float CP = C + Pu, CM = C - Pu, D = C - AA;
-            float h[8] = {CP + Qv, CP - Qv, CM + Qv, CM - Qv, CP - BB, CM - BB, D + Qv, D - Qv};
+            const float X1 = C + Pu, X2 = C - Pu, X3 = C - BB, X4 = C - AA;
+            const float aP = fabsf(Pu), aQ = fabsf(Qv);
+            const float g = fminf(fminf(C - aP - aQ, X3 - aP), fminf(X4 - aQ, (kCap + gmin) - C));
+            const float P2 = Pu * Pu, Q2 = Qv * Qv;
+            const float q1 = fmaf(X1, X1, -Q2), q2 = fmaf(X2, X2, -Q2);
+            const float q3 = fmaf(X3, X3, -P2), q4 = fmaf(X4, X4, -Q2);
+            const float n12 = fmaf(X1, q2, X2 * q1), d12 = q1 * q2;
+            const float n34 = fmaf(X3, q4, X4 * q3), d34 = q3 * q4;
+            float f = fmaf(n12, d34, n34 * d12) * __builtin_amdgcn_rcpf(d12 * d34);
+            // (a wave-uniform branch: the clamped form only when a lane needs it)
+            if (__ballot(g < gmin)) {
+                float h[8] = {X1 + Qv, X1 - Qv, X2 + Qv, X2 - Qv, X1 - BB, X2 - BB, X4 + Qv, X4 - Qv};
 #pragma unroll
-            for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
-            reciprocal_sum<8>(h, acc, acc2);
+                for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
+                const float slow = 0.5f * reciprocal_total<8>(h);
+                f = g >= gmin ? f : slow;
+            }
+            half += f;
         });
     } else if constexpr (PT != 0) {
         static_assert(PT == 7, "quadrotor layout: 7 points");
         if (p.shape_kind == kShapeMirroredAxis) {
-            // a_{6-i} = -a_i: the pair shares |e|^2 - r^2 + a_i^2, and its two
-            // points differ in the sign of 2 a_i e.u.  o.z = -r^2 + a_0^2, so
-            // the first pair's shared term is b0 = |e|^2 + o.z itself.
+            // a_{6-i} = -a_i, and |a_0| is the largest |a_i| (the host checks
+            // both): pair i shares c_i = |e|^2 - r^2 + a_i^2 and its two points
+            // differ in the sign of d_i = 2 a_i e.u.  o.z = -r^2 + a_0^2, so
+            // c_0 = b0 = |e|^2 + o.z itself and c_i = b0 + (a_i^2 - a_0^2) <= b0;
+            // the middle point lies between points 0 and 6, so its h is at most
+            // theirs, and every h is at most 2 b0.  Cap: b0 <= 1e5, so 7 values
+            // of h <= 2e5 multiply below 1.3e37.
+            constexpr float kCap = 1.0e5f;
             const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
             const float AM = sa2[3], DM = ss[3] - ss[0];
+            const float aA0 = fabsf(A0), aA1 = fabsf(A1), aA2 = fabsf(A2);
+            const float nA0 = -(A0 * A0), nA1 = -(A1 * A1), nA2 = -(A2 * A2);
             run([&](const float4 o) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
                 const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
                 const float b1 = b0 + D1, b2 = b0 + D2;
-                float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), b0 + fmaf(AM, pu, DM),
-                              fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
+                const float hm = b0 + fmaf(AM, pu, DM);
+                const float apu = fabsf(pu);
+                const float g = fminf(fminf(fmaf(-aA0, apu, b0), fmaf(-aA1, apu, b1)),
+                                      fminf(fminf(fmaf(-aA2, apu, b2), hm), (kCap + gmin) - b0));
+                const float pu2 = pu * pu;
+                const float q0 = fmaf(b0, b0, nA0 * pu2), q1 = fmaf(b1, b1, nA1 * pu2);
+                const float q2 = fmaf(b2, b2, nA2 * pu2);
+                const float n01 = fmaf(b0, q1, b1 * q0), d01 = q0 * q1;
+                const float n2m = fmaf(b2, hm, 0.5f * q2), d2m = q2 * hm;
+                float f = fmaf(n01, d2m, n2m * d01) * __builtin_amdgcn_rcpf(d01 * d2m);
+                // (a wave-uniform branch: the clamped form only when a lane needs it)
+                if (__ballot(g < gmin)) {
+                    float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), hm,
+                                  fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
 #pragma unroll
-                for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
-                reciprocal_sum<7>(h, acc, acc2);
+                    for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
+                    const float slow = 0.5f * reciprocal_total<7>(h);
+                    f = g >= gmin ? f : slow;
+                }
+                half += f;
             });
         } else {
             run([&](const float4 o) __attribute__((always_inline)) {
@@ -594,6 +655,7 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         });
     }
     acc += acc2;
+    acc = fmaf(2.0f, half, acc);
     if (with_map) {
 #pragma unroll
         for (int i = 0; i < PM; ++i) {

@@ -162,7 +162,8 @@ constexpr int fixed_points(int model) { return model == MPPI_CAR ? 8 : 7; }
 // midpoints of a rectangle centred on the reference point, in the order
 // (a, b), (a, -b), (-a, b), (-a, -b), (a, 0), (-a, 0), (0, b), (0, -b).
 // Quadrotors, 1: every point on the body axis (b = 0); 2: moreover points
-// 0, 1, 2 are the mirror images of points 6, 5, 4 (a_i = -a_{6-i}).
+// 0, 1, 2 are the mirror images of points 6, 5, 4 (a_i = -a_{6-i}) and point
+// 0 lies farthest from the centre (|a_0| >= |a_i|).
 enum ShapeForm : int32_t { kShapeGeneral = 0, kShapeLayout = 1, kShapeMirroredAxis = 2 };
 
 inline int32_t shape_form(int model, int P, const float (*sh)[2])
@@ -179,6 +180,9 @@ inline int32_t shape_form(int model, int P, const float (*sh)[2])
         if (sh[i][1] != 0.0f) return kShapeGeneral;
     for (int i = 0; i < 3; ++i)
         if (sh[i][0] != -sh[6 - i][0]) return kShapeLayout;
+    const float a0 = sh[0][0] < 0.0f ? -sh[0][0] : sh[0][0];
+    for (int i = 1; i < 4; ++i)
+        if ((sh[i][0] < 0.0f ? -sh[i][0] : sh[i][0]) > a0) return kShapeLayout;
     return kShapeMirroredAxis;
 }
 
