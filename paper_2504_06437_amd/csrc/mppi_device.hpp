@@ -279,17 +279,35 @@ __device__ __forceinline__ float reciprocal_total(const float* h)
 
 // Bilinear costmap sample between cell centres, clamped to the edge cells.
 // (gx, gy) are continuous cell coordinates; any float input stays in bounds.
-__device__ __forceinline__ float sdf_sample(const float* __restrict__ sdf, int W, int H, float gx, float gy)
+// With the four-texel layout (sdf4: for every square between four cell
+// centres, its four values in one 16-byte record) a sample is one load
+// instead of four scattered ones; the arithmetic, and so the result, is the
+// same.
+__device__ __forceinline__ float sdf_sample(const DevParams& p, float gx, float gy)
 {
+    const int W = p.map_w, H = p.map_h;
     gx = fminf(fmaxf(gx, 0.0f), (float)(W - 1));
     gy = fminf(fmaxf(gy, 0.0f), (float)(H - 1));
     const int i0 = min((int)floorf(gx), W - 2);
     const int j0 = min((int)floorf(gy), H - 2);
     const float fx = gx - (float)i0, fy = gy - (float)j0;
-    const float* r0 = sdf + (size_t)j0 * W + i0;
-    const float* r1 = r0 + W;
-    const float top = fmaf(fx, r0[1] - r0[0], r0[0]);
-    const float bot = fmaf(fx, r1[1] - r1[0], r1[0]);
+    float s00, s01, s10, s11;
+    if (p.sdf4) {
+        const float4 c = p.sdf4[(size_t)j0 * (W - 1) + i0];
+        s00 = c.x;
+        s01 = c.y;
+        s10 = c.z;
+        s11 = c.w;
+    } else {
+        const float* r0 = p.sdf + (size_t)j0 * W + i0;
+        const float* r1 = r0 + W;
+        s00 = r0[0];
+        s01 = r0[1];
+        s10 = r1[0];
+        s11 = r1[1];
+    }
+    const float top = fmaf(fx, s01 - s00, s00);
+    const float bot = fmaf(fx, s11 - s10, s10);
     return fmaf(fy, bot - top, top);
 }
 
@@ -381,7 +399,8 @@ struct TileLds {
     int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
                       // [5], [6] the batched kernel's unit counters
     // chunk slots, two buffers each (buffer b at offset b * cs):
-    float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, 0)
+    float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, costmap terms of the
+                      // chunk two behind: sum B(sdf) or, with the indicator, the smallest sdf)
     float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
     float* bval;      // [2][cs] per (step, sample): fused barrier
     float2* nz;       // [T][S] the tile's noise, when it fits (else null)
@@ -484,9 +503,9 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
         const float u = p.shape[i0][0], w = p.shape[i0][1];
         const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
         const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
-        acc_a += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pax, inv_res, offx), fmaf(pay, inv_res, offy)),
+        acc_a += barrier_rcp(sdf_sample(p, fmaf(pax, inv_res, offx), fmaf(pay, inv_res, offy)),
                              p.h_eps);
-        acc_b += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(pbx, inv_res, offx), fmaf(pby, inv_res, offy)),
+        acc_b += barrier_rcp(sdf_sample(p, fmaf(pbx, inv_res, offx), fmaf(pby, inv_res, offy)),
                              p.h_eps);
     }
     return make_float2(acc_a, acc_b);
@@ -494,8 +513,7 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 
 // Part of the fused barrier of one pose, lane sp of a group of js = 2^lg
 // lanes: every shape point against obstacles sp, sp + js, sp + 2 js, ...
-// below J (read from LDS), plus, with a costmap, the costmap terms of shape
-// points sp, sp + js, ... below P.
+// below J (read from LDS).  The costmap terms are formed apart (map_terms).
 //
 // With e = pose - o, the heading u = (cos, sin) and its normal v, a shape
 // point with body offset (a, b) gives
@@ -512,8 +530,7 @@ __device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
 template <int MODEL, int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
-                                                    const float* sb2, const float* ss, float4 pose, int sp, int lg,
-                                                    bool with_map, float inv_res, float offx, float offy)
+                                                    const float* sb2, const float* ss, float4 pose, int sp, int lg)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
     const float eps = p.h_eps;
@@ -656,30 +673,48 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
     }
     acc += acc2;
     acc = fmaf(2.0f, half, acc);
-    if (with_map) {
+    return acc;
+}
+
+// The costmap terms of one pose (every shape point): sum_i B(sdf(p_i)), or
+// with the indicator the smallest sdf(p_i).  Four shape points' reads are in
+// flight at a time; the body offsets come from the parameter block (uniform
+// scalar loads), so the loop holds no per-point registers.
+template <int PT, bool IND>
+__device__ __forceinline__ float map_terms(const DevParams& p, int P, float4 pose, float inv_res, float offx,
+                                           float offy)
+{
+    constexpr int G = 4;
+    const int np = PT ? PT : P;
+    const float cs = pose.z, sn = pose.w;
+    float acc = IND ? INFINITY : 0.0f;
+#pragma unroll 1
+    for (int i0 = 0; i0 < np; i0 += G) {
+        float v[G];
 #pragma unroll
-        for (int i = 0; i < PM; ++i) {
-            if ((PT || i < P) && (i & (js - 1)) == sp) {
-                const float px = pose.x + 0.5f * fmaf(sa2[i], cs, -sb2[i] * sn);
-                const float py = pose.y + 0.5f * fmaf(sa2[i], sn, sb2[i] * cs);
-                acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
-                                   eps);
-            }
+        for (int j = 0; j < G; ++j) {
+            const int i = min(i0 + j, np - 1);
+            const float a = p.shape[i][0], b = p.shape[i][1];
+            const float px = pose.x + fmaf(a, cs, -b * sn);
+            const float py = pose.y + fmaf(a, sn, b * cs);
+            v[j] = sdf_sample(p, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy));
         }
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j < np) acc = IND ? fminf(acc, v[j]) : acc + barrier_rcp(v[j], p.h_eps);
     }
     return acc;
 }
 
 // The comparison controllers' constraint test of one pose (Sec. IV-A's
 // weighted indicator): lane sp of a group of js = 2^lg lanes returns the
-// smallest h of every shape point against obstacles sp, sp + js, ... and, with
-// a costmap, of shape points sp, sp + js, ... on the map (+inf when it has
-// none); the group's minimum decides whether the pose violates a constraint
-// (h < 0).  General form h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2, as the
-// runtime-P barrier takes it.
+// smallest h of every shape point against obstacles sp, sp + js, ... (+inf
+// when it has none); with the costmap's smallest value (map_terms), the
+// group's minimum decides whether the pose violates a constraint (h < 0).
+// General form h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2, as the runtime-P
+// barrier takes it.
 __device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
-                                                const float* sb2, const float* ss, float4 pose, int sp, int lg,
-                                                bool with_map, float inv_res, float offx, float offy)
+                                                const float* sb2, const float* ss, float4 pose, int sp, int lg)
 {
     constexpr int PM = MPPI_PMAX;
     const float cs = pose.z, sn = pose.w;
@@ -702,16 +737,6 @@ __device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLd
         }
     }
     lo = fminf(lo, lo2);
-    if (with_map) {
-#pragma unroll
-        for (int i = 0; i < PM; ++i) {
-            if (i < P && (i & (js - 1)) == sp) {
-                const float px = pose.x + 0.5f * tx[i];
-                const float py = pose.y + 0.5f * ty[i];
-                lo = fminf(lo, sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)));
-            }
-        }
-    }
     return lo;
 }
 
@@ -737,7 +762,7 @@ __device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLd
 // shuffles.
 // Inputs, poses and barrier values are double-buffered by chunk parity.
 // ---------------------------------------------------------------------------
-template <int MODEL, int S, int PT, bool SC, bool IND>
+template <int MODEL, int S, int PT, bool SC, bool IND, bool MAP>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
     static_assert(!IND || PT == 0, "the indicator runs on the runtime-P tile");
@@ -786,8 +811,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         L.ref[i] = a == 0 ? (float)((double)v - ox) : a == 1 ? (float)((double)v - oy) : v;
     }
     float inv_res = 0.0f, offx = 0.0f, offy = 0.0f;
-    const bool has_map = p.sdf != nullptr;
-    if (has_map) {
+    // MAP: the controller has a costmap (p.sdf set); the tiles without one
+    // carry none of its code
+    if constexpr (MAP) {
         inv_res = (float)(1.0 / (double)p.map_res);
         offx = (float)((ox - (double)p.map_x0) / (double)p.map_res - 0.5);
         offy = (float)((oy - (double)p.map_y0) / (double)p.map_res - 0.5);
@@ -879,7 +905,18 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
             float f0, f1;
             Model<MODEL>::inputs(p, s0, s1, f0, f1);
-            dst[idx] = make_float4(f0, f1, cw0 * u.x * v0 + cw1 * u.y * v1, 0.0f);
+            const float ccost = cw0 * u.x * v0 + cw1 * u.y * v1;
+            if constexpr (MAP) {
+                // (.w is left alone: it carries the costmap terms of the chunk
+                // two behind, from the pool's map units to the barrier-state
+                // stage)
+                float* d = reinterpret_cast<float*>(dst + idx);
+                d[0] = f0;
+                d[1] = f1;
+                d[2] = ccost;
+            } else {
+                dst[idx] = make_float4(f0, f1, ccost, 0.0f);
+            }
             if (keep_noise) L.nz[t * S + s] = z;
         }
     };
@@ -916,9 +953,11 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     auto beta_chunk = [&](int c) __attribute__((always_inline)) {
         const int n = chunk_len(c);
         const float* bv = L.bval + (c & 1) * L.cs;
+        [[maybe_unused]] const float4* mv = L.in + (c & 1) * L.cs;
         float nb = bv[tid];
         for (int tt = 0; tt < n; ++tt) {
-            const float b = nb;
+            float b = nb;
+            if constexpr (MAP) b = IND ? fminf(b, mv[tt * S + tid].w) : b + mv[tt * S + tid].w;
             if (tt + 1 < n) nb = bv[(tt + 1) * S + tid];
             if constexpr (IND) {
                 if (b < 0.0f) two_sum_acc(S_hi, S_lo, p.collision_weight);
@@ -974,21 +1013,30 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         const int items = chunk_len(c) * S;
         const int lg = (lg_pack >> (c == 0 ? 0 : c == nch - 1 ? 8 : 4)) & 15;
         const int nsp = 1 << lg;
-        const int units = ((items << lg) + kWave - 1) / kWave;
+        // obstacle units (nsp lanes per item), then, with a costmap, map units
+        // (one item per lane, every shape point: their reads all in flight at
+        // once, away from the long obstacle units)
+        const int ounits = ((items << lg) + kWave - 1) / kWave;
+        const int units = ounits + (MAP ? (items + kWave - 1) / kWave : 0);
         const float4* pz = L.pose + (c & 1) * L.cs;
         float* bv = L.bval + (c & 1) * L.cs;
+        [[maybe_unused]] float4* mv = L.in + (c & 1) * L.cs;
         auto unit = [&](int u) __attribute__((always_inline)) {
+            if constexpr (MAP) {
+                if (u >= ounits) {
+                    const int item = (u - ounits) * kWave + lane;
+                    if (item < items) mv[item].w = map_terms<PT, IND>(p, P, pz[item], inv_res, offx, offy);
+                    return;
+                }
+            }
             const int g = u * kWave + lane;
             const int item = g >> lg, sp = g & (nsp - 1);
             float part = IND ? INFINITY : 0.0f;
             if constexpr (IND) {
-                if (item < items)
-                    part = clearance_pose(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res, offx, offy);
+                if (item < items) part = clearance_pose(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
                 for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
             } else {
-                if (item < items)
-                    part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, has_map, inv_res,
-                                                         offx, offy);
+                if (item < items) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
                 for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
             }
             if (sp == 0 && item < items) bv[item] = part;
@@ -1258,7 +1306,7 @@ __device__ __forceinline__ void touch_kernargs()
     asm volatile("" ::"s"(t));
 }
 
-template <int MODEL, int S, int PT, bool IND>
+template <int MODEL, int S, int PT, bool IND, bool MAP>
 __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1274,16 +1322,24 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0[i];
     }
     xs.parity = a.parity;
-    rollout_tile<MODEL, S, PT, true, IND>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
+    rollout_tile<MODEL, S, PT, true, IND, MAP>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
 
 template <int MODEL, int S>
 __device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.cost_mode == MPPI_COST_INDICATOR) rollout_tile<MODEL, S, 0, false, true>(p, tile, xs, smem);
-    else if (p.P == PD && p.shape_kind != kShapeGeneral) rollout_tile<MODEL, S, PD, false, false>(p, tile, xs, smem);
-    else rollout_tile<MODEL, S, 0, false, false>(p, tile, xs, smem);
+    const bool map = p.sdf != nullptr;
+    if (p.cost_mode == MPPI_COST_INDICATOR) {
+        if (map) rollout_tile<MODEL, S, 0, false, true, true>(p, tile, xs, smem);
+        else rollout_tile<MODEL, S, 0, false, true, false>(p, tile, xs, smem);
+    } else if (p.P == PD && p.shape_kind != kShapeGeneral) {
+        if (map) rollout_tile<MODEL, S, PD, false, false, true>(p, tile, xs, smem);
+        else rollout_tile<MODEL, S, PD, false, false, false>(p, tile, xs, smem);
+    } else {
+        if (map) rollout_tile<MODEL, S, 0, false, false, true>(p, tile, xs, smem);
+        else rollout_tile<MODEL, S, 0, false, false, false>(p, tile, xs, smem);
+    }
 }
 
 template <int MODEL>
@@ -1338,12 +1394,18 @@ template <int MODEL, int S>
 hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    if (p.cost_mode == MPPI_COST_INDICATOR)
-        hipLaunchKernelGGL((k_rollout<MODEL, S, 0, true>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
-    else if (p.P == PD && p.shape_kind != kShapeGeneral)
-        hipLaunchKernelGGL((k_rollout<MODEL, S, PD, false>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
-    else
-        hipLaunchKernelGGL((k_rollout<MODEL, S, 0, false>), dim3(p.tiles), dim3(kRollBlock), lds, s, p, a);
+    const dim3 g(p.tiles), b(kRollBlock);
+    const bool map = p.sdf != nullptr;
+    if (p.cost_mode == MPPI_COST_INDICATOR) {
+        if (map) hipLaunchKernelGGL((k_rollout<MODEL, S, 0, true, true>), g, b, lds, s, p, a);
+        else hipLaunchKernelGGL((k_rollout<MODEL, S, 0, true, false>), g, b, lds, s, p, a);
+    } else if (p.P == PD && p.shape_kind != kShapeGeneral) {
+        if (map) hipLaunchKernelGGL((k_rollout<MODEL, S, PD, false, true>), g, b, lds, s, p, a);
+        else hipLaunchKernelGGL((k_rollout<MODEL, S, PD, false, false>), g, b, lds, s, p, a);
+    } else {
+        if (map) hipLaunchKernelGGL((k_rollout<MODEL, S, 0, false, true>), g, b, lds, s, p, a);
+        else hipLaunchKernelGGL((k_rollout<MODEL, S, 0, false, false>), g, b, lds, s, p, a);
+    }
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct DevParams {
     const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window
     const float* obs;        // [J][3] cx, cy, r (world frame)
     const float* sdf;        // [map_h][map_w] or null
+    const float4* sdf4;      // [map_h-1][map_w-1] four-texel records of sdf (null: read sdf itself)
     const float* xref;       // [T+1][n] world frame
     float* U;                // [2][T][2] warm start, double-buffered by iteration parity
     float* Unext;            // [T][2] where the update writes the shifted warm start instead of the
@@ -286,6 +287,7 @@ hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids,
                                 size_t lds, hipStream_t s);
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s);
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s);
+hipError_t launch_sdf_cells(const float* sdf, int W, int H, float4* out, hipStream_t s);
 int batch_rollout_blocks_per_cu(int model, size_t lds);
 bool tile_samples_supported(int S);
 

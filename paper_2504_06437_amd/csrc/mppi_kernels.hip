@@ -217,7 +217,7 @@ __device__ void explore_ctrl(const DevParams& p, const X0& xs, unsigned char* sm
         if (has_map && lane < P) {
             const float px = fmaf(p.shape[lane][0], q.z, fmaf(-p.shape[lane][1], q.w, q.x));
             const float py = fmaf(p.shape[lane][0], q.w, fmaf(p.shape[lane][1], q.z, q.y));
-            acc += barrier_rcp(sdf_sample(p.sdf, p.map_w, p.map_h, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
+            acc += barrier_rcp(sdf_sample(p, fmaf(px, inv_res, offx), fmaf(py, inv_res, offy)),
                                p.h_eps);
         }
         acc = wave_sum_f(acc);
@@ -278,6 +278,18 @@ __global__ __launch_bounds__(kExpBlock) void k_batch_explore(const DevParams* __
     for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[c].x0[i];
     xs.parity = in[c].parity;
     explore_ctrl(ps[c], xs, smem);
+}
+
+// The four-texel records of a costmap: record (i, j), 0 <= i < W-1,
+// 0 <= j < H-1, holds the values at cell centres (i, j), (i+1, j), (i, j+1),
+// (i+1, j+1).
+__global__ __launch_bounds__(256) void k_sdf_cells(const float* __restrict__ sdf, int W, int H, float4* out)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (W - 1) * (H - 1)) return;
+    const int j = idx / (W - 1), i = idx - j * (W - 1);
+    const float* r0 = sdf + (size_t)j * W + i;
+    out[idx] = make_float4(r0[0], r0[1], r0[W], r0[W + 1]);
 }
 
 // w_k = e_k f_b(k) / eta: the weights the update used.
@@ -393,6 +405,13 @@ hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids,
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s)
 {
     hipLaunchKernelGGL(k_weights, dim3((p.K + 255) / 256), dim3(256), 0, s, p, d_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_sdf_cells(const float* sdf, int W, int H, float4* out, hipStream_t s)
+{
+    const int n = (W - 1) * (H - 1);
+    hipLaunchKernelGGL(k_sdf_cells, dim3((n + 255) / 256), dim3(256), 0, s, sdf, W, H, out);
     return hipGetLastError();
 }
 

@@ -265,6 +265,7 @@ mppi_ctrl::~mppi_ctrl()
     for (void* ptr : allocations) (void)hipFree(ptr);
     if (d_obs) (void)hipFree(d_obs);
     if (d_sdf) (void)hipFree(d_sdf);
+    if (d_sdf4) (void)hipFree(d_sdf4);
     if (h_res) (void)hipHostFree(h_res);
     for (hipEvent_t e : prof_events)
         if (e) (void)hipEventDestroy(e);
@@ -602,6 +603,7 @@ extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float
     CHECK_HANDLE(h);
     if (!sdf) {
         h->p.sdf = nullptr;
+        h->p.sdf4 = nullptr;
         h->p.map_w = h->p.map_h = 0;
         ++h->version;
         return MPPI_OK;
@@ -620,7 +622,17 @@ extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float
         h->sdf_bytes = bytes;
     }
     HIP_TRY(h, hipMemcpy(h->d_sdf, sdf, bytes, mem == MPPI_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    const size_t bytes4 = sizeof(float4) * (size_t)(W - 1) * (H - 1);
+    if (bytes4 > h->sdf4_bytes) {
+        if (h->d_sdf4) (void)hipFree(h->d_sdf4);
+        h->d_sdf4 = nullptr;
+        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&h->d_sdf4), bytes4));
+        h->sdf4_bytes = bytes4;
+    }
+    HIP_TRY(h, launch_sdf_cells(h->d_sdf, W, H, h->d_sdf4, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->p.sdf = h->d_sdf;
+    h->p.sdf4 = h->d_sdf4;
     h->p.map_w = W;
     h->p.map_h = H;
     h->p.map_x0 = x0;

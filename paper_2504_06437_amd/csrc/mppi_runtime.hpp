@@ -25,6 +25,8 @@ struct mppi_ctrl {
     int obs_cap = 0;
     float* d_sdf = nullptr;
     size_t sdf_bytes = 0;
+    float4* d_sdf4 = nullptr;        // four-texel records of the costmap
+    size_t sdf4_bytes = 0;
     dbas::HostResult* h_res = nullptr;
     // kernel timing (mppi_profile_*): event triples per recorded iteration
     bool profiling = false;
