@@ -84,6 +84,7 @@ struct mppi_batch {
         lds_exp = 0;
         for (int c = 0; c < n; ++c) {
             params[c] = ctrls[c]->p;
+            params[c].lg_pack = tile_lg_pack(params[c].J, params[c].T, params[c].n, params[c].spt, params[c].P);
             versions[c] = ctrls[c]->version;
             const DevParams& p = params[c];
             const double cost = tile_cost(p.spt, p.K, p.T, p.P, p.J);

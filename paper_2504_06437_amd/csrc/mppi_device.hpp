@@ -398,13 +398,14 @@ struct TileLds {
     double* slots;    // [16] block-reduction slots
     int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
                       // [5], [6] the batched kernel's unit counters
-    // chunk slots, two buffers each (buffer b at offset b * cs):
+    // chunk slots, two buffers each (buffer b at offset b * cb, cb = cs + kXSlots):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, costmap terms of the
                       // chunk two behind: sum B(sdf) or, with the indicator, the smallest sdf)
     float4* pose;     // [2][cs] per (step, sample): (x, y, cos theta, sin theta)
     float* bval;      // [2][cs] per (step, sample): fused barrier
     float2* nz;       // [T][S] the tile's noise, when it fits (else null)
-    int cs;
+    int cs;           // (step, sample) items of a full chunk
+    int cb;           // buffer stride: cs + kXSlots
 };
 
 __device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int n, int cs, bool keep_noise)
@@ -425,12 +426,13 @@ __device__ __forceinline__ TileLds carve(unsigned char* smem, int J, int T, int 
     L.work = reinterpret_cast<int*>(smem + off);
     off += 64;
     L.cs = cs;
+    L.cb = cs + kXSlots;
     L.in = reinterpret_cast<float4*>(smem + off);
-    off += (size_t)2 * cs * 16;
+    off += (size_t)2 * L.cb * 16;
     L.pose = reinterpret_cast<float4*>(smem + off);
-    off += (size_t)2 * cs * 16;
+    off += (size_t)2 * L.cb * 16;
     L.bval = reinterpret_cast<float*>(smem + off);
-    off += (size_t)2 * cs * 4;
+    off += (size_t)2 * L.cb * 4;
     L.nz = keep_noise ? reinterpret_cast<float2*>(smem + off) : nullptr;
     return L;
 }
@@ -466,49 +468,6 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
         r.y += s[2 * i + 1];
     }
     return r;
-}
-
-// This thread's share, over threads [first, block), of the fused barrier at
-// two (local-frame) poses a and b: every shape point against obstacles
-// i0, i0 + stride, ... (PM = compile-time bound on P), and with a costmap
-// the costmap term of shape point i0.
-template <int PM>
-__device__ float2 fused_barrier_share2(const DevParams& p, const TileLds& L, int P, int first, float ax, float ay,
-                                       float ath, float bx, float by, float bth, float inv_res, float offx,
-                                       float offy)
-{
-    const int J = p.J;
-    const int i0 = (int)threadIdx.x - first;
-    // a wave with no obstacle and no costmap point to take is done
-    if ((int)(threadIdx.x & ~(kWave - 1)) - first >= max(J, p.sdf != nullptr ? P : 0)) return make_float2(0.0f, 0.0f);
-    float sa, ca, sb, cb;
-    heading_sincos(ath, sa, ca);
-    heading_sincos(bth, sb, cb);
-    float acc_a = 0.0f, acc_b = 0.0f;
-    for (int j = i0; j < J; j += kRollBlock - first) {
-        const float4 o = L.obs[j];
-#pragma unroll
-        for (int i = 0; i < PM; ++i) {
-            if (i < P) {
-                const float u = p.shape[i][0], w = p.shape[i][1];
-                const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
-                const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
-                const float dax = pax - o.x, day = pay - o.y, dbx = pbx - o.x, dby = pby - o.y;
-                acc_a += barrier_rcp(fmaf(dax, dax, fmaf(day, day, o.w)), p.h_eps);
-                acc_b += barrier_rcp(fmaf(dbx, dbx, fmaf(dby, dby, o.w)), p.h_eps);
-            }
-        }
-    }
-    if (p.sdf != nullptr && i0 >= 0 && i0 < P) {
-        const float u = p.shape[i0][0], w = p.shape[i0][1];
-        const float pax = ax + (u * ca - w * sa), pay = ay + (u * sa + w * ca);
-        const float pbx = bx + (u * cb - w * sb), pby = by + (u * sb + w * cb);
-        acc_a += barrier_rcp(sdf_sample(p, fmaf(pax, inv_res, offx), fmaf(pay, inv_res, offy)),
-                             p.h_eps);
-        acc_b += barrier_rcp(sdf_sample(p, fmaf(pbx, inv_res, offx), fmaf(pby, inv_res, offy)),
-                             p.h_eps);
-    }
-    return make_float2(acc_a, acc_b);
 }
 
 // Part of the fused barrier of one pose, lane sp of a group of js = 2^lg
@@ -835,7 +794,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     [[maybe_unused]] int my_pool = 1;                   // pool waves on this wave's SIMD
     [[maybe_unused]] int serve[kSimdsPerCU] = {0, 1, 2, 3};   // the SIMD that serves each unit class
 
-    float beta0 = 0.0f, beta_d = 0.0f;      // fused B(h(x0)), fused B(h(x_d)), formed below
+    float beta0 = 0.0f, beta_d = 0.0f;      // fused B(h(x0)), fused B(h(x_d)), formed in stage 1
 
     // ---- setup: lanes 0..S-1 own one sample each ----
     const bool owner = tid < S;
@@ -894,7 +853,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // inputs of every (step, sample) of chunk c, over threads [first, block)
     auto inputs_chunk = [&](int c, int first) __attribute__((always_inline)) {
         const int t0 = chunk_t0(c), items = chunk_len(c) * S;
-        float4* dst = L.in + (c & 1) * L.cs;
+        float4* dst = L.in + (c & 1) * L.cb;
         for (int idx = tid - first; idx < items; idx += kRollBlock - first) {
             const int s = idx & (S - 1), t = t0 + idx / S;
             const int kk = tile * S + s;
@@ -924,8 +883,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // dynamics of chunk c (owner lanes): poses to LDS, tracking + control cost
     auto dynamics_chunk = [&](int c) __attribute__((always_inline)) {
         const int t0 = chunk_t0(c), n = chunk_len(c);
-        const float4* src = L.in + (c & 1) * L.cs;
-        float4* pz = L.pose + (c & 1) * L.cs;
+        const float4* src = L.in + (c & 1) * L.cb;
+        float4* pz = L.pose + (c & 1) * L.cb;
         float4 nin = src[tid];
         for (int tt = 0; tt < n; ++tt) {
             const float4 in = nin;
@@ -952,8 +911,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // constraint (the pool left each step's smallest h in bval)
     auto beta_chunk = [&](int c) __attribute__((always_inline)) {
         const int n = chunk_len(c);
-        const float* bv = L.bval + (c & 1) * L.cs;
-        [[maybe_unused]] const float4* mv = L.in + (c & 1) * L.cs;
+        const float* bv = L.bval + (c & 1) * L.cb;
+        [[maybe_unused]] const float4* mv = L.in + (c & 1) * L.cb;
         float nb = bv[tid];
         for (int tt = 0; tt < n; ++tt) {
             float b = nb;
@@ -968,34 +927,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    // Split of the fused-barrier items of a chunk of `items` (step, sample)
-    // items over nsp = 2^lg lanes each: among the splits that give every wave
-    // of the noise pool a unit, the one whose units, spread over the CU's
-    // SIMDs, cost least: ceil(units / SIMDs) units, each of ceil(J / nsp)
-    // obstacles x P pairs plus a fixed part (pose, shape transform,
-    // reduction: about 8 pairs' worth).  Without such a split, the finest.
-    auto split_lg = [&](int items) {
-        int lg = 0;
-        long best = -1;
-        for (int l = 0; l <= 6 && (1 << l) <= max(J, 1); ++l) {
-            const long units = ((long)(items << l) + kWave - 1) / kWave;
-            if (units < kRollWaves - DW) {
-                if (best < 0) lg = l;                    // the finest so far
-                continue;
-            }
-            const long per_lane = (J + (1 << l) - 1) >> l;
-            const long cost = (units + kSimdsPerCU - 1) / kSimdsPerCU * (per_lane * P + 8);
-            if (best < 0 || cost < best) {
-                best = cost;
-                lg = l;
-            }
-        }
-        return lg;
-    };
-    // A tile's chunks have at most three lengths (the first, the middle ones,
-    // the last), so their splits are chosen once, packed 4 bits each.
-    const int lg_pack = split_lg(chunk_len(0) * S) | (nch > 2 ? split_lg(tc * S) << 4 : 0) |
-                        (nch > 1 ? split_lg(chunk_len(nch - 1) * S) << 8 : 0);
+    // The barrier splits of the tile's chunks (tile_lg_pack): set by the host
+    // in the parameter block, else formed here.
+    const int lg_pack = (p.lg_pack & kLgPackSet) ? p.lg_pack : tile_lg_pack(J, T, NS, S, P);
 
     // Fused barrier of every (step, sample) of chunk c, in units of one wave.
     // With SC the units are shared out by SIMD, not taken first come first
@@ -1011,21 +945,25 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // counter.  Which wave computes a unit never changes its arithmetic.
     auto barrier_chunk = [&](int c) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
+        // with the barrier state, chunk 0 also takes the poses of x0 and x_d
+        // (its extra slots)
+        const int xitems = (!IND && c == 0) ? kXSlots : 0;
+        const int all = items + xitems;
         const int lg = (lg_pack >> (c == 0 ? 0 : c == nch - 1 ? 8 : 4)) & 15;
         const int nsp = 1 << lg;
         // obstacle units (nsp lanes per item), then, with a costmap, map units
         // (one item per lane, every shape point: their reads all in flight at
         // once, away from the long obstacle units)
-        const int ounits = ((items << lg) + kWave - 1) / kWave;
-        const int units = ounits + (MAP ? (items + kWave - 1) / kWave : 0);
-        const float4* pz = L.pose + (c & 1) * L.cs;
-        float* bv = L.bval + (c & 1) * L.cs;
-        [[maybe_unused]] float4* mv = L.in + (c & 1) * L.cs;
+        const int ounits = ((all << lg) + kWave - 1) / kWave;
+        const int units = ounits + (MAP ? (all + kWave - 1) / kWave : 0);
+        const float4* pz = L.pose + (c & 1) * L.cb;
+        float* bv = L.bval + (c & 1) * L.cb;
+        [[maybe_unused]] float4* mv = L.in + (c & 1) * L.cb;
         auto unit = [&](int u) __attribute__((always_inline)) {
             if constexpr (MAP) {
                 if (u >= ounits) {
                     const int item = (u - ounits) * kWave + lane;
-                    if (item < items) mv[item].w = map_terms<PT, IND>(p, P, pz[item], inv_res, offx, offy);
+                    if (item < all) mv[item].w = map_terms<PT, IND>(p, P, pz[item], inv_res, offx, offy);
                     return;
                 }
             }
@@ -1035,11 +973,12 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             if constexpr (IND) {
                 if (item < items) part = clearance_pose(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
                 for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
+                if (sp == 0 && item < items) bv[item] = part;
             } else {
-                if (item < items) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
+                if (item < all) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
                 for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
+                if (sp == 0 && item < all) bv[item] = part;
             }
-            if (sp == 0 && item < items) bv[item] = part;
         };
         if constexpr (SC) {
             if (wave < DW) return;
@@ -1060,23 +999,10 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    // The first chunk's inputs, on the upper half of the workgroup, while the
-    // threads below J form beta_0 = fused B(h(x0)) and beta_d = fused
-    // B(h(x_d)), x_d = x_ref[T]; the block reduction's barriers then order
-    // both before stage 0.
+    // The first chunk's inputs, on the upper half of the workgroup.
     if (tid >= kRollBlock / 2) inputs_chunk(0, kRollBlock / 2);
-    if constexpr (IND) {
-        lds_barrier();                      // no barrier state: beta_0 = beta_d = 0
-    } else {
-        const float2 b0d = block_sum_f2<kRollWaves>(
-            fused_barrier_share2<PM>(p, L, P, 0, 0.0f, 0.0f, xs.v[2], L.ref[T * NS], L.ref[T * NS + 1],
-                                     L.ref[T * NS + 2], inv_res, offx, offy),
-            L.slots);
-        beta0 = b0d.x;
-        beta_d = b0d.y;
-        beta = beta0;
-    }
-    // (the SIMD counts are final: the block reductions since have synchronised)
+    lds_barrier();
+    // (the SIMD counts are final: the barriers since have synchronised)
     if constexpr (SC) {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
         const int osimd = __builtin_amdgcn_readfirstlane(L.work[4]);
@@ -1092,9 +1018,27 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             if (tid == 0) L.work[5 + ((st_k + 1) & 1)] = 0;      // counter of the next stage
         }
         if (wave < DW) {
+            if (!IND && owner && st_k == 2) {
+                // beta_0 and beta_d, formed in stage 1 in chunk 0's extra
+                // slots (buffer 0 is next written in stage 3)
+                const int i0 = tc0 * S;
+                beta0 = L.bval[i0] + (MAP ? L.in[i0].w : 0.0f);
+                beta_d = L.bval[i0 + 1] + (MAP ? L.in[i0 + 1].w : 0.0f);
+                beta = beta0;
+            }
             if (owner && st_k >= 2) beta_chunk(st_k - 2);
             if (owner && st_k < nch) dynamics_chunk(st_k);
         } else {
+            if (!IND && st_k == 0 && wave == kRollWaves - 1 && lane < kXSlots) {
+                // beta_0 and beta_d are the fused barriers of the poses of x0
+                // and x_d = x_ref[T]: chunk 0 carries them in its two extra
+                // slots, so the barrier units of stage 1 form them (this wave
+                // has no noise to draw in stage 0)
+                const float* xd = L.ref + T * NS;
+                float sn, cn;
+                heading_sincos(lane == 0 ? xs.v[2] : xd[2], sn, cn);
+                L.pose[tc0 * S + lane] = lane == 0 ? make_float4(0.0f, 0.0f, cn, sn) : make_float4(xd[0], xd[1], cn, sn);
+            }
             if (st_k + 1 < nch) inputs_chunk(st_k + 1, POOL0);
         }
         if (st_k >= 1 && st_k <= nch) barrier_chunk(st_k - 1);

@@ -67,6 +67,8 @@ struct DevParams {
     int32_t cost_mode;       // MPPI_COST_DBAS or MPPI_COST_INDICATOR (no barrier state)
     float collision_weight;  // weight of the collision indicator
     int32_t shape_kind;      // ShapeForm: the layout form the model's fixed-P tile may use
+    int32_t lg_pack;         // the rollout's barrier splits (tile_lg_pack | kLgPackSet), or 0:
+                             //   the kernel forms them itself
     double beta_d_weight;    // R_B sum_{t=1..T} c_t / beta_d, the common barrier-state cost per unit of beta_d
     const float* sgf_coef;   // [T][2m+1] smoothing weights of step t over its window
     const float* obs;        // [J][3] cx, cy, r (world frame)
@@ -195,6 +197,14 @@ __host__ __device__ inline int obstacle_slots(int J) { return J > 0 ? J : 1; }
 constexpr size_t kLdsLimit = 65536;     // dynamic LDS budget of one rollout workgroup
 constexpr int kChunkSlotsMax = 2048;    // most (step, sample) slots in one horizon chunk
 
+// Per (step, sample) slot, double-buffered: inputs (float4), pose (float4),
+// fused barrier (float).
+constexpr int kSlotBytes = 2 * (16 + 16 + 4);
+// Each chunk buffer holds two slots beyond its (step, sample) items: chunk 0
+// carries the poses of x0 and x_d = x_ref[T] there, whose fused barriers are
+// beta_0 and beta_d.
+constexpr int kXSlots = 2;
+
 // LDS bytes of a rollout tile apart from the chunk slots.
 __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
 {
@@ -206,12 +216,9 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
     b += 64;                                    // pool waves per SIMD, owner SIMD, unit counters
+    b += (size_t)kXSlots * kSlotBytes;          // two extra slots per chunk buffer (x0, x_d)
     return b;
 }
-
-// Per (step, sample) slot, double-buffered: inputs (float4), pose (float4),
-// fused barrier (float).
-constexpr int kSlotBytes = 2 * (16 + 16 + 4);
 
 // First chunk of the rollout pipeline: about a tenth of the horizon.
 __host__ __device__ inline int tile_first_chunk(int T) { return (T + 9) / 10; }
@@ -229,6 +236,49 @@ __host__ __device__ inline int tile_chunk_steps(int J, int T, int n, int S)
     if (tc > fit) tc = fit;
     if (tc < 1) tc = 1;
     return (int)tc;
+}
+
+// Split of the fused-barrier items of a chunk of `items` (step, sample)
+// items over nsp = 2^lg lanes each, for a tile whose first DW waves own its
+// samples: among the splits that give every wave of the noise pool a unit,
+// the one whose units, spread over the CU's four SIMDs, cost least:
+// ceil(units / 4) units, each of ceil(J / nsp) obstacles x P pairs plus a
+// fixed part (pose, shape transform, reduction: about 8 pairs' worth).
+// Without such a split, the finest.
+__host__ __device__ inline int tile_split_lg(int items, int J, int P, int DW)
+{
+    int lg = 0;
+    long best = -1;
+    for (int l = 0; l <= 6 && (1 << l) <= (J > 1 ? J : 1); ++l) {
+        const long units = ((long)items * (1L << l) + kWave - 1) / kWave;
+        if (units < kRollBlock / kWave - DW) {
+            if (best < 0) lg = l;                        // the finest so far
+            continue;
+        }
+        const long per_lane = (J + (1 << l) - 1) >> l;
+        const long cost = (units + 3) / 4 * (per_lane * P + 8);
+        if (best < 0 || cost < best) {
+            best = cost;
+            lg = l;
+        }
+    }
+    return lg;
+}
+
+constexpr int kLgPackSet = 1 << 12;
+
+// The splits of a tile's chunks, which have at most three lengths (the
+// first, the middle ones, the last), packed 4 bits each, with kLgPackSet.
+__host__ __device__ inline int tile_lg_pack(int J, int T, int n, int S, int P)
+{
+    const int tc = tile_chunk_steps(J, T, n, S);
+    if (tc == 0) return kLgPackSet;
+    const int tc0 = tile_first_chunk(T) < tc ? tile_first_chunk(T) : tc;
+    const int nch = 1 + (T - tc0 + tc - 1) / tc;
+    const int DW = (S + kWave - 1) / kWave;
+    const int last = nch == 1 ? tc0 : T - (tc0 + (nch - 2) * tc);
+    return kLgPackSet | tile_split_lg(tc0 * S, J, P, DW) | (nch > 2 ? tile_split_lg(tc * S, J, P, DW) << 4 : 0) |
+           (nch > 1 ? tile_split_lg(last * S, J, P, DW) << 8 : 0);
 }
 
 // Does a tile of S samples fit the rollout's LDS budget: at least one horizon

@@ -315,8 +315,10 @@ __global__ __launch_bounds__(256) void k_philox_words(DevParams p, uint64_t coun
 
 bool tile_samples_supported(int S) { return S >= 16 && S <= kMaxTile && (S & (S - 1)) == 0; }
 
-hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s)
+hipError_t launch_rollout(const DevParams& p0, const StepArgs& a, hipStream_t s)
 {
+    DevParams p = p0;
+    p.lg_pack = tile_lg_pack(p.J, p.T, p.n, p.spt, p.P);
     const size_t lds = tile_lds_bytes(p.J, p.T, p.n, p.spt);
     switch (p.model) {
     case MPPI_QUAD6: return launch_rollout_quad6(p, a, lds, s);

@@ -205,6 +205,7 @@ size_t mppi_server::stage(Slot& sl, UnitGroups* groups, int* nrows_out, size_t* 
         Request& rq = reqs[picks[i].ticket];
         mppi_ctrl* h = rb.h;
         DevParams q = h->p;
+        q.lg_pack = tile_lg_pack(q.J, q.T, q.n, q.spt, q.P);
         char* base = d_arena + picks[i].offset;
         const ScratchLayout& L = rb.layout;
         q.du = q.export_noise ? reinterpret_cast<float*>(base + L.du) : nullptr;
