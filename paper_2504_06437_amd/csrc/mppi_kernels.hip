@@ -26,9 +26,15 @@ namespace {
 // coalesced over tiles; it writes U*, the shifted warm start (Alg. 1 closing
 // loop) into the other half of the double buffer and u0*; the workgroup of
 // row 0 also records the iteration in the controller's state.
+// host: what goes to the pinned host result block -- kHostNone: nothing;
+// kHostPlain: u0, status and counter, seen by the host after the launch
+// completes; kHostMark: the same, then the completion mark behind one
+// system-scope fence, for a host thread that spins on the mark.
 // ---------------------------------------------------------------------------
+enum HostOut { kHostNone = 0, kHostPlain = 1, kHostMark = 2 };
+
 __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float* u0_dev, int32_t* status_dev,
-                            bool mark, double* sf, double* slots)
+                            int host, double* sf, double* slots)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -49,6 +55,15 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
 #pragma unroll
     for (int i = 0; i < kPre; ++i) pre[i] = (has_row && lane + i * kWave < nt) ? row[lane + i * kWave] : 0.0;
     const float u_in = has_row ? Uin[r] : 0.0f;
+    // the state words the first workgroup updates at the end (the rollout
+    // does not write them)
+    uint64_t ctr = 0;
+    uint32_t it0 = 0;
+    if (first && tid == 0) {
+        ctr = st->counter;
+        it0 = st->iter;
+    }
+    HostResult* res = host != kHostNone ? p.res : nullptr;
     const bool one = nt <= kUpdBlock;
     double rb1 = INFINITY, eb1 = 0.0, fl1 = 0.0;
     if (one && tid < nt) {
@@ -108,34 +123,34 @@ __device__ void update_rows(const DevParams& p, int row0, uint32_t parity, float
             }
             if (t == 0) {
                 if (u0_dev) u0_dev[r] = us;
-                if (p.res) {
-                    p.res->u0[r] = us;
-                    if (mark) __threadfence_system();   // before the completion mark below
-                }
+                if (first) reinterpret_cast<float*>(slots)[2 * kUpdWaves * 2 + r] = us;   // for thread 0
             }
         }
     }
     if (first) {
-        __syncthreads();                        // rows 0 and 1 (u0) are written by this workgroup
+        __syncthreads();                        // rows 0 and 1 (u0) are in LDS
         if (tid == 0) {
-            const uint64_t c = st->counter;
             const int status = ok ? MPPI_OK : MPPI_E_NUMERIC;
-            st->last_counter = c;
-            if (ok) st->counter = c + 1u;
+            st->last_counter = ctr;
+            if (ok) st->counter = ctr + 1u;
             st->rho = rho;
             st->eta = eta;
             st->status = status;
             st->fp64_tiles = (int32_t)n64s;
             if (status_dev) *status_dev = status;
-            const uint32_t it = st->iter + 1u;
+            const uint32_t it = it0 + 1u;
             st->iter = it;
-            if (p.res) {
-                p.res->status = status;
-                p.res->counter = c;
-                if (mark) {
+            if (res) {
+                const float* u0l = reinterpret_cast<const float*>(slots) + 2 * kUpdWaves * 2;
+                res->u0[0] = u0l[0];
+                res->u0[1] = u0l[1];
+                res->status = status;
+                res->counter = ctr;
+                if (host == kHostMark) {
+                    // u0, status and counter are this thread's own stores: one
+                    // fence orders them before the mark
                     __threadfence_system();
-                    p.res->seq = it;
-                    __threadfence_system();     // push the mark out now, not at kernel end
+                    res->seq = it;
                 }
             }
         }
@@ -240,8 +255,9 @@ __device__ void explore_ctrl(const DevParams& p, const X0& xs, unsigned char* sm
 __global__ __launch_bounds__(kUpdBlock) void k_update(DevParams p, StepArgs a)
 {
     __shared__ double sf[kMaxTiles];
-    __shared__ double slots[2 * kUpdWaves];
-    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.status_dev, a.mark != 0, sf, slots);
+    __shared__ double slots[2 * kUpdWaves + 1];       // + u0 of rows 0 and 1
+    update_rows(p, blockIdx.x * kUpdWaves, a.parity, a.u0_dev, a.status_dev, a.mark ? kHostMark : kHostNone, sf,
+                slots);
 }
 
 // One workgroup per (controller, four control rows) of the batch.
@@ -250,10 +266,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_batch_update(const DevParams* __r
                                                             const BatchIn* __restrict__ in, float* u0s)
 {
     __shared__ double sf[kMaxTiles];
-    __shared__ double slots[2 * kUpdWaves];
+    __shared__ double slots[2 * kUpdWaves + 1];       // + u0 of rows 0 and 1
     const RowUnit ru = units[blockIdx.x];
-    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, nullptr, false,
-                sf, slots);
+    update_rows(ps[ru.ctrl], ru.row0, in[ru.ctrl].parity, u0s ? u0s + (size_t)ru.ctrl * kM : nullptr, nullptr,
+                kHostPlain, sf, slots);
 }
 
 __global__ __launch_bounds__(kExpBlock) void k_explore(DevParams p, StepArgs a)
