@@ -602,11 +602,13 @@ extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float
 {
     CHECK_HANDLE(h);
     if (!sdf) {
+        const bool had = h->p.sdf != nullptr;
         h->p.sdf = nullptr;
         h->p.sdf4 = nullptr;
         h->p.map_w = h->p.map_h = 0;
         ++h->version;
-        return MPPI_OK;
+        // the costmap is part of the tile shape's key: choose again
+        return had ? h->retile() : MPPI_OK;
     }
     if (W < 2 || H < 2 || (long)W * H > (1L << 26)) return h->fail(MPPI_E_INVALID, "costmap must be at least 2x2");
     if (!(res > 0) || !std::isfinite(res) || !std::isfinite(x0) || !std::isfinite(y0))
@@ -631,6 +633,7 @@ extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float
     }
     HIP_TRY(h, launch_sdf_cells(h->d_sdf, W, H, h->d_sdf4, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const bool had = h->p.sdf != nullptr;
     h->p.sdf = h->d_sdf;
     h->p.sdf4 = h->d_sdf4;
     h->p.map_w = W;
@@ -639,7 +642,8 @@ extern "C" int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float
     h->p.map_y0 = y0;
     h->p.map_res = res;
     ++h->version;
-    return MPPI_OK;
+    // the costmap is part of the tile shape's key: choose again
+    return had ? MPPI_OK : h->retile();
 }
 
 extern "C" int mppi_set_reference(mppi_t* h, const float* x_ref, int32_t mem)

@@ -47,7 +47,7 @@ def main(argv=None) -> int:
         c = Controller(wl["params"])
         c.load_workload(wl)
         c.close()
-        if (i + 1) % 50 == 0:
+        if (i + 1) % 10 == 0:
             print(f"[tune] {i + 1}/{len(wls)} shapes", flush=True)
     rows = {}
     with open(cache) as fh:
