@@ -745,6 +745,26 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const CtrlState* cs_in = p.st;
     const float S_e = cs_in->S_e;
     const uint64_t ctr = cs_in->counter;
+    const uint32_t c_lo = (uint32_t)ctr, c_hi = (uint32_t)(ctr >> 32);
+
+    // the Philox words of sample kk at step t (Sec. IV-C: counter (k, t, iteration))
+    // (the key words, uniform over the tile, pass through an empty asm
+    // statement, so that the twenty round keys are formed per item by scalar
+    // adds instead of being held in scalar registers across the whole stage
+    // loop, where they crowded out other values into reloads)
+    auto philox_at = [&](int kk, int t) __attribute__((always_inline)) {
+        uint32_t k0 = __builtin_amdgcn_readfirstlane(p.seed_lo), k1 = __builtin_amdgcn_readfirstlane(p.seed_hi);
+        asm volatile("" : "+s"(k0), "+s"(k1));
+        return philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), k0, k1);
+    };
+    // Chunk 0's words are drawn first, on the upper half of the workgroup (two
+    // items per thread), while the staging below waits on memory.
+    const int items0 = tc0 * S;
+    const int j0 = tid - kRollBlock / 2;
+    uint4 w0 = make_uint4(0u, 0u, 0u, 0u), w1 = w0;
+    if (j0 >= 0 && j0 < items0) w0 = philox_at(tile * S + (j0 & (S - 1)), j0 / S);
+    if (j0 >= 0 && j0 + kRollBlock / 2 < items0)
+        w1 = philox_at(tile * S + ((j0 + kRollBlock / 2) & (S - 1)), (j0 + kRollBlock / 2) / S);
 
     const float* Uin = p.U + (size_t)(xs.parity & 1u) * T * kM;
 
@@ -792,7 +812,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         pslot = __builtin_amdgcn_readfirstlane(pslot);
     }
     [[maybe_unused]] int my_pool = 1;                   // pool waves on this wave's SIMD
-    [[maybe_unused]] int serve[kSimdsPerCU] = {0, 1, 2, 3};   // the SIMD that serves each unit class
+    [[maybe_unused]] int my_classes = 0;                // bit cl: this wave's SIMD serves unit class cl
 
     float beta0 = 0.0f, beta_d = 0.0f;      // fused B(h(x0)), fused B(h(x_d)), formed in stage 1
 
@@ -806,7 +826,6 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const bool normal_law = p.sampling == MPPI_SAMPLE_NORMAL;
     const float cw0 = p.sigma[0] > 0.0f ? p.gamma_u / (S_e * p.sigma[0] * p.sigma[0]) : 0.0f;
     const float cw1 = p.sigma[1] > 0.0f ? p.gamma_u / (S_e * p.sigma[1] * p.sigma[1]) : 0.0f;
-    const uint32_t c_lo = (uint32_t)ctr, c_hi = (uint32_t)(ctr >> 32);
 
     float x[NS];
     x[0] = 0.0f;
@@ -839,15 +858,32 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     auto chunk_len = [&](int c) { return c == 0 ? tc0 : min(tc, T - chunk_t0(c)); };
 
     // the noise of sample kk at step t (Sec. IV-C mixture, scaled per Alg. 1)
-    // (the key words, uniform over the tile, pass through an empty asm
-    // statement, so that the twenty round keys are formed per item by scalar
-    // adds instead of being held in scalar registers across the whole stage
-    // loop, where they crowded out other values into reloads)
-    auto noise_at = [&](int kk, int t) __attribute__((always_inline)) {
-        uint32_t k0 = __builtin_amdgcn_readfirstlane(p.seed_lo), k1 = __builtin_amdgcn_readfirstlane(p.seed_hi);
-        asm volatile("" : "+s"(k0), "+s"(k1));
-        const uint4 r = philox4x32_10(make_uint4((uint32_t)kk, (uint32_t)t, c_lo, c_hi), k0, k1);
+    auto noise_of = [&](uint4 r) __attribute__((always_inline)) {
         return nln_pair(r, scale0, scale1, p.mu_ln, p.sigma_ln, normal_law);
+    };
+    auto noise_at = [&](int kk, int t) __attribute__((always_inline)) { return noise_of(philox_at(kk, t)); };
+
+    // the inputs of item idx = (t - t0) S + s of a chunk from its noise z
+    auto store_input = [&](float4* dst, int idx, int t, int s, float2 z) __attribute__((always_inline)) {
+        const float2 u = L.U[t];
+        const float v0 = u.x + z.x, v1 = u.y + z.y;
+        const float s0 = fminf(fmaxf(v0, p.u_min[0]), p.u_max[0]);
+        const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
+        float f0, f1;
+        Model<MODEL>::inputs(p, s0, s1, f0, f1);
+        const float ccost = cw0 * u.x * v0 + cw1 * u.y * v1;
+        if constexpr (MAP) {
+            // (.w is left alone: it carries the costmap terms of the chunk
+            // two behind, from the pool's map units to the barrier-state
+            // stage)
+            float* d = reinterpret_cast<float*>(dst + idx);
+            d[0] = f0;
+            d[1] = f1;
+            d[2] = ccost;
+        } else {
+            dst[idx] = make_float4(f0, f1, ccost, 0.0f);
+        }
+        if (keep_noise) L.nz[t * S + s] = z;
     };
 
     // inputs of every (step, sample) of chunk c, over threads [first, block)
@@ -856,27 +892,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         float4* dst = L.in + (c & 1) * L.cb;
         for (int idx = tid - first; idx < items; idx += kRollBlock - first) {
             const int s = idx & (S - 1), t = t0 + idx / S;
-            const int kk = tile * S + s;
-            const float2 z = noise_at(kk, t);
-            const float2 u = L.U[t];
-            const float v0 = u.x + z.x, v1 = u.y + z.y;
-            const float s0 = fminf(fmaxf(v0, p.u_min[0]), p.u_max[0]);
-            const float s1 = fminf(fmaxf(v1, p.u_min[1]), p.u_max[1]);
-            float f0, f1;
-            Model<MODEL>::inputs(p, s0, s1, f0, f1);
-            const float ccost = cw0 * u.x * v0 + cw1 * u.y * v1;
-            if constexpr (MAP) {
-                // (.w is left alone: it carries the costmap terms of the chunk
-                // two behind, from the pool's map units to the barrier-state
-                // stage)
-                float* d = reinterpret_cast<float*>(dst + idx);
-                d[0] = f0;
-                d[1] = f1;
-                d[2] = ccost;
-            } else {
-                dst[idx] = make_float4(f0, f1, ccost, 0.0f);
-            }
-            if (keep_noise) L.nz[t * S + s] = z;
+            store_input(dst, idx, t, s, noise_at(tile * S + s, t));
         }
     };
 
@@ -982,9 +998,9 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         };
         if constexpr (SC) {
             if (wave < DW) return;
-#pragma unroll
-            for (int cl = 0; cl < kSimdsPerCU; ++cl) {
-                if (serve[cl] != simd) continue;
+            // the classes this SIMD serves, in turn (one copy of the unit code)
+            for (int cls = my_classes; cls != 0; cls &= cls - 1) {
+                const int cl = __builtin_ctz(cls);
                 for (int u = cl + kSimdsPerCU * pslot; u < units; u += kSimdsPerCU * my_pool) unit(u);
             }
         } else {
@@ -999,19 +1015,28 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
-    // The first chunk's inputs, on the upper half of the workgroup.
-    if (tid >= kRollBlock / 2) inputs_chunk(0, kRollBlock / 2);
+    // The first chunk's inputs, on the upper half of the workgroup, from the
+    // words drawn at entry (and drawn here for any item beyond two per thread).
+    if (j0 >= 0) {
+        constexpr int H = kRollBlock / 2;
+        if (j0 < items0) store_input(L.in, j0, j0 / S, j0 & (S - 1), noise_of(w0));
+        if (j0 + H < items0) store_input(L.in, j0 + H, (j0 + H) / S, (j0 + H) & (S - 1), noise_of(w1));
+        for (int idx = j0 + 2 * H; idx < items0; idx += H)
+            store_input(L.in, idx, idx / S, idx & (S - 1), noise_at(tile * S + (idx & (S - 1)), idx / S));
+    }
     lds_barrier();
     // (the SIMD counts are final: the barriers since have synchronised)
     if constexpr (SC) {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
         const int osimd = __builtin_amdgcn_readfirstlane(L.work[4]);
+        int mine = 0;
 #pragma unroll
         for (int cl = 0; cl < kSimdsPerCU; ++cl) {
             int sv = (osimd + kSimdsPerCU - 1 - cl) & (kSimdsPerCU - 1);
             for (int t = 0; t < kSimdsPerCU && L.work[sv] == 0; ++t) sv = (sv + 1) & (kSimdsPerCU - 1);
-            serve[cl] = __builtin_amdgcn_readfirstlane(sv);
+            if (sv == simd) mine |= 1 << cl;
         }
+        my_classes = __builtin_amdgcn_readfirstlane(mine);
     }
     for (int st_k = 0; st_k <= nch + 1; ++st_k) {
         if constexpr (!SC) {
