@@ -713,7 +713,10 @@ extern "C" int mppi_profile_enable(mppi_t* h, int32_t every)
     if (on && h->prof_events.empty()) {
         HIP_TRY(h, hipSetDevice(h->device));
         h->prof_events.resize(3 * 4096, nullptr);
-        for (auto& e : h->prof_events) HIP_TRY(h, hipEventCreate(&e));
+        // timing only: the host reads them after synchronising the stream, so
+        // they need no system-scope fence (which would add a cache write-back
+        // to every timed launch)
+        for (auto& e : h->prof_events) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     h->profiling = on;
     h->prof_every = on ? every : 1;

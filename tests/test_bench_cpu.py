@@ -93,12 +93,17 @@ def test_committed_records_match_the_kernel_source():
     were taken on.  When the kernel source has changed since, the bench
     reports null for them until the counters are taken again: skipped, with
     the reason, rather than failed."""
+    stale = []
     for name in ("traffic.json", "counters.json"):
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
-        r = rec["rollout"][WORKLOAD]
-        assert set(r) >= {"kernel_source_sha256_16", "kernels", "dispatches"}, name
-        if r["kernel_source_sha256_16"] != bench._kernel_digest():
-            pytest.skip(f"profiles/{name} predates the kernel source; the bench reports null until re-profiled")
+        for workload in (bench.workload_name(W.quad_large()), WORKLOAD):
+            r = rec["rollout"][workload]
+            assert set(r) >= {"kernel_source_sha256_16", "kernels", "dispatches"}, (name, workload)
+            if r["kernel_source_sha256_16"] != bench._kernel_digest():
+                stale.append(f"{name} [{workload}]")
+    if stale:
+        pytest.skip("records that predate the kernel source (the bench reports null for them until "
+                    "re-profiled): " + ", ".join(stale))
 
 
 def test_algorithmic_flops_follow_the_per_term_table():
