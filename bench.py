@@ -24,7 +24,9 @@ bracketed by device synchronisation.  Also reported:
   * the batched path: 64 mixed controllers in one graph-captured persistent
     launch vs the same 64 stepped one after another through the plain path;
   * the served path: 256 robots sending Poisson 50 Hz request streams to the
-    continuous-batching server for 60 s (p50/p99 arrival-to-response);
+    continuous-batching server for 60 s (p50/p99 arrival-to-response), and
+    the server's sustained rate with every robot keeping one request in
+    flight for 10 s;
   * the paper's controller and its two baselines (Vanilla MPPI, Log-MPPI) at
     the paper's mission sizes (M = 1024, N = 20), and the closed-loop
     missions with each;
@@ -358,6 +360,51 @@ def bench_served(seconds=60.0, n_robots=256, rate_hz=50.0, seed=4, budget=256 <<
     }
 
 
+
+def bench_served_saturation(seconds=10.0, n_robots=256, seed=4, budget=256 << 20, streams=3):
+    """The server's sustained rate: every robot (sizes as the mixed batch)
+    keeps one request in flight, submitting its next state as soon as the
+    previous response arrives, for `seconds`.  Requests/s and rollout-steps/s
+    here are what the server completes when the offered load always exceeds
+    it; latency is submit -> response."""
+    from paper_2504_06437_amd.controller import Server
+    from paper_2504_06437_amd.plant import advance
+    wls = W.batch(n_robots, seed)
+    srv = Server(budget_bytes=budget, max_slots=256, streams=streams, max_batch=64)
+    ids = [srv.add_robot(wl["params"], wl["obstacles"]) for wl in wls]
+    states = [wl["x0"].copy() for wl in wls]
+    for i, wl in enumerate(wls):
+        srv.wait(srv.submit(ids[i], states[i], W.reference(wl, states[i])))
+    work = [wl["params"]["K"] * wl["params"]["T"] for wl in wls]
+    t0 = srv.now()
+    tickets = [srv.submit(ids[r], states[r], None, t0) for r in range(n_robots)]
+    lat, served_steps, n_done = [], 0, 0
+    t_end = t0
+    while True:
+        now = srv.now()
+        if now - t0 >= seconds:
+            break
+        for r in range(n_robots):
+            res = srv.poll(tickets[r])
+            if res is None:
+                continue
+            u0, l, st = res
+            lat.append(l)
+            served_steps += work[r]
+            n_done += 1
+            states[r] = advance(wls[r]["params"], states[r], u0)
+            t_end = srv.now()
+            tickets[r] = srv.submit(ids[r], states[r], None, t_end)
+    for r in range(n_robots):
+        srv.wait(tickets[r])
+    stats = srv.stats()
+    srv.close()
+    span = t_end - t0
+    return {"robots": n_robots, "seconds": seconds, "requests": n_done, "requests_per_s": n_done / span,
+            "rollout_steps_per_s": served_steps / span, "p50_ms": 1e3 * percentile(lat, 50),
+            "p99_ms": 1e3 * percentile(lat, 99), "launches": stats["launches"], "mean_batch": stats["mean_batch"],
+            "streams": streams}
+
 def host_cpu():
     model = None
     try:
@@ -656,6 +703,9 @@ def main():
     if not args.no_served:
         print(f"[bench] served path: 256 robots x 50 Hz for {args.serve_seconds:g} s", file=sys.stderr, flush=True)
         out["served"] = bench_served(args.serve_seconds)
+        print("[bench] served path at saturation: 256 robots, one request in flight each, 10 s", file=sys.stderr,
+              flush=True)
+        out["served_saturation"] = bench_served_saturation()
     if not args.no_missions:
         from paper_2504_06437_amd import mission
         print(f"[bench] missions: {args.mission_runs} closed-loop runs each, three controllers", file=sys.stderr,
