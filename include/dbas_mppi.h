@@ -91,7 +91,13 @@ typedef enum { MPPI_COST_DBAS = 0, MPPI_COST_INDICATOR = 1 } mppi_cost_mode;
  *  - u_min/u_max: actuator limits, applied inside the dynamics.
  *  - h_eps in [1e-9, 1e6].
  *  - tile_samples: samples per rollout workgroup (16, 32, 64, 128 or 256);
- *    0 lets the autotuner choose (per model, K, T, J, P).
+ *    0 chooses per shape (model, K, T, J, P, costmap, smoothing, cost
+ *    mode): from the process cache, the MPPI_TUNE_CACHE file, the
+ *    tile_table.txt shipped beside the library, else by timing the
+ *    candidates (and appending the choice to the cache file).  The choice is
+ *    made again when the obstacle count changes or a costmap is set or
+ *    cleared.  The tile size fixes the order of the tile's reductions, so a
+ *    shape found in a table gives the same results in every process.
  *  - export_noise: 0 (default) -- the noise lives only inside the rollout
  *    kernel and is never stored; 1 -- every iteration also writes it to
  *    device memory (K*T*8 bytes) so that mppi_get_noise can return it.
@@ -207,7 +213,9 @@ int mppi_set_obstacles(mppi_t* h, int32_t J, const float* cxcyr, int32_t mem);
 /* Optional signed-distance costmap, row-major sdf[H][W] in metres, cell
  * (col i, row j) centred at (x0 + (i+1/2) res, y0 + (j+1/2) res), sampled
  * bilinearly and clamped to the edge; each shape point adds B(sdf) to the
- * fused barrier.  sdf = NULL clears it.  Errors: INVALID (W or H < 2, res <= 0). */
+ * fused barrier.  sdf = NULL clears it.  Setting or clearing the costmap
+ * chooses the tile size again (tile_samples = 0).  Errors: INVALID (W or H
+ * < 2, res <= 0). */
 int mppi_set_costmap(mppi_t* h, int32_t W, int32_t H, float x0, float y0, float res,
                      const float* sdf, int32_t mem);
 
