@@ -503,7 +503,8 @@ def load_counters(kernel: str, workload: str):
     """VALU figures from rocprofv3 SQ counters, if recorded for the current
     kernel source (profiles/counters.json)."""
     r = _load_record("counters.json", kernel, workload)
-    return {k: r[k] for k in ("valu_busy", "valu_insts_per_wave", "wait_frac")} if r else None
+    keys = ("active_valu_ratio", "valu_insts_per_wave", "wait_frac", "executed_flops_per_launch")
+    return {k: r[k] for k in keys if k in r} if r else None
 
 
 def copy_calibration(mib: int, copies: int = 5):
@@ -569,10 +570,14 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
 
 
 def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
-    """VALU use of the rollout from SQ counters (two rocprofv3 passes).  Every
-    wave lives for the whole launch (one tile per CU, four waves per SIMD), so
-    a SIMD's VALU busy fraction is the VALU-active time of its waves over one
-    wave's lifetime: SQ_ACTIVE_INST_VALU / (SQ_WAVE_CYCLES / 4)."""
+    """VALU use of the rollout from SQ counters (two rocprofv3 passes):
+    instructions per wave, the waiting share, the transcendental share, and
+    the executed FP32 FLOPs per launch, 64 lanes x (2 FMA + ADD + MUL) over
+    the FP32 instruction counts (every lane of a wave counted; the counters
+    count wave instructions).  Also SQ_ACTIVE_INST_VALU / (SQ_WAVE_CYCLES /
+    4), reported as a ratio: with four waves per SIMD living the whole
+    launch it would be the SIMD's VALU busy fraction, but on gfx950 it
+    exceeds 1, so the two counters are not in the units that reading needs."""
     act, n, names = _pmc_mean(sq1_dir, "SQ_ACTIVE_INST_VALU", "k_rollout")
     wcyc, _, _ = _pmc_mean(sq1_dir, "SQ_WAVE_CYCLES", "k_rollout")
     waves, _, _ = _pmc_mean(sq1_dir, "SQ_WAVES", "k_rollout")
@@ -582,13 +587,20 @@ def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
     rec = {}
     if os.path.exists(out_path):
         rec = json.load(open(out_path))
-    rec.setdefault("rollout", {})[workload] = {
-        "valu_busy": act / (wcyc / 4.0), "valu_insts_per_wave": insts / waves, "wait_frac": wait / wcyc,
-        "trans_share": trans / insts, "dispatches": n, "kernels": names, "kernel_source_sha256_16": _kernel_digest(),
-    }
+    r = {"active_valu_ratio": act / (wcyc / 4.0), "valu_insts_per_wave": insts / waves, "wait_frac": wait / wcyc,
+         "trans_share": trans / insts, "dispatches": n, "kernels": names, "kernel_source_sha256_16": _kernel_digest()}
+    try:
+        fma, _, _ = _pmc_mean(sq2_dir, "SQ_INSTS_VALU_FMA_F32", "k_rollout")
+        add, _, _ = _pmc_mean(sq2_dir, "SQ_INSTS_VALU_ADD_F32", "k_rollout")
+        mul, _, _ = _pmc_mean(sq2_dir, "SQ_INSTS_VALU_MUL_F32", "k_rollout")
+        r.update({"fma_f32": fma, "add_f32": add, "mul_f32": mul,
+                  "executed_flops_per_launch": 64.0 * (2.0 * fma + add + mul)})
+    except SystemExit:
+        pass
+    rec.setdefault("rollout", {})[workload] = r
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
-    return rec["rollout"][workload]
+    return r
 
 
 def update_bytes(p: dict, tiles: int) -> int:
@@ -669,6 +681,10 @@ def main():
                   {"update_kernel_ms_mean": r["update_ms_mean"], "timed_every": 1 if args.workload == "c2" else PROFILE_EVERY})
     rl["traffic"] = load_traffic("rollout", name)
     rl["valu"] = load_counters("rollout", name)
+    if rl["valu"] and "executed_flops_per_launch" in rl["valu"]:
+        ex = rl["valu"]["executed_flops_per_launch"] / (r["rollout_ms_mean"] * 1e-3) / 1e12
+        rl["valu"]["executed_tflops"] = ex
+        rl["valu"]["executed_frac"] = ex / PEAK_FP32_VECTOR_TFLOPS
     out = {
         "metric": METRIC, "value": r["rollout_steps_per_s"], "unit": "rollout-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,

@@ -74,18 +74,24 @@ def test_counter_summary(tmp_path, monkeypatch):
     _counter_csv(tmp_path / "sq1", [(3, ROLLOUT, "SQ_ACTIVE_INST_VALU", 600.0), (3, ROLLOUT, "SQ_WAVE_CYCLES", 4000.0),
                                     (3, ROLLOUT, "SQ_WAVES", 4.0), (3, ROLLOUT, "SQ_INSTS_VALU", 1200.0),
                                     (3, ROLLOUT, "SQ_WAIT_ANY", 2000.0)])
-    _counter_csv(tmp_path / "sq2", [(4, ROLLOUT, "SQ_INSTS_VALU_TRANS_F32", 60.0)])
+    # 500 FMA, 200 ADD and 100 MUL wave instructions: 64 * (1000 + 200 + 100) FLOPs
+    _counter_csv(tmp_path / "sq2", [(4, ROLLOUT, "SQ_INSTS_VALU_TRANS_F32", 60.0),
+                                    (4, ROLLOUT, "SQ_INSTS_VALU_FMA_F32", 500.0),
+                                    (4, ROLLOUT, "SQ_INSTS_VALU_ADD_F32", 200.0),
+                                    (4, ROLLOUT, "SQ_INSTS_VALU_MUL_F32", 100.0)])
     out = tmp_path / "counters.json"
     r = bench.summarize_counters(str(tmp_path / "sq1"), str(tmp_path / "sq2"), WORKLOAD, str(out))
-    assert r["valu_busy"] == pytest.approx(0.6)
+    assert r["active_valu_ratio"] == pytest.approx(0.6)
     assert r["valu_insts_per_wave"] == pytest.approx(300.0)
     assert r["wait_frac"] == pytest.approx(0.5) and r["trans_share"] == pytest.approx(0.05)
+    assert r["executed_flops_per_launch"] == pytest.approx(64 * 1300.0)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
     os.replace(out, tmp_path / "profiles" / "counters.json")
-    assert bench.load_counters("rollout", WORKLOAD) == {"valu_busy": pytest.approx(0.6),
+    assert bench.load_counters("rollout", WORKLOAD) == {"active_valu_ratio": pytest.approx(0.6),
                                                         "valu_insts_per_wave": pytest.approx(300.0),
-                                                        "wait_frac": pytest.approx(0.5)}
+                                                        "wait_frac": pytest.approx(0.5),
+                                                        "executed_flops_per_launch": pytest.approx(64 * 1300.0)}
 
 
 def test_committed_records_match_the_kernel_source():
