@@ -36,6 +36,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dbas {
 namespace {
@@ -397,7 +398,8 @@ struct TileLds {
     double* e;        // [kMaxTile] tile exponentials
     double* slots;    // [16] block-reduction slots
     int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
-                      // [5], [6] the batched kernel's unit counters
+                      // [5], [6] the batched kernel's unit counters, [7] the bits of
+                      // the largest |o|^2 over the obstacles
     // chunk slots, two buffers each (buffer b at offset b * cb, cb = cs + kXSlots):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, costmap terms of the
                       // chunk two behind: sum B(sdf) or, with the indicator, the smallest sdf)
@@ -489,7 +491,8 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
 template <int MODEL, int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
-                                                    const float* sb2, const float* ss, float4 pose, int sp, int lg)
+                                                    const float* sb2, const float* ss, float4 pose, int sp, int lg,
+                                                    float omax2)
 {
     constexpr int PM = PT ? PT : MPPI_PMAX;
     const float eps = p.h_eps;
@@ -564,17 +567,27 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         });
     } else if constexpr (PT != 0) {
         static_assert(PT == 7, "quadrotor layout: 7 points");
-        if (p.shape_kind == kShapeMirroredAxis) {
-            // a_{6-i} = -a_i, and |a_0| is the largest |a_i| (the host checks
-            // both): pair i shares c_i = |e|^2 - r^2 + a_i^2 and its two points
-            // differ in the sign of d_i = 2 a_i e.u.  o.z = -r^2 + a_0^2, so
-            // c_0 = b0 = |e|^2 + o.z itself and c_i = b0 + (a_i^2 - a_0^2) <= b0;
-            // the middle point lies between points 0 and 6, so its h is at most
-            // theirs, and every h is at most 2 b0.  Cap: b0 <= 1e5, so 7 values
-            // of h <= 2e5 multiply below 1.3e37.
-            constexpr float kCap = 1.0e5f;
+        // The mirrored-axis form: a_{6-i} = -a_i, and |a_0| is the largest
+        // |a_i| (the host checks both): pair i shares c_i = |e|^2 - r^2 + a_i^2
+        // and its two points differ in the sign of d_i = 2 a_i e.u.  o.z =
+        // -r^2 + a_0^2, so c_0 = b0 = |e|^2 + o.z itself and c_i = b0 + (a_i^2 -
+        // a_0^2) <= b0.  It runs when the middle point is the centre (a_3 = 0,
+        // the paper's body: h_m = b0 - a_0^2 <= b0) and no obstacle of this unit
+        // can pass the cap: every h is then at most 2 b0 <= 2e5, and 7 of them
+        // multiply below 1.3e37.  The cap holds for the whole unit when
+        // 2 |pose|^2 + 2 max_j |o_j|^2 + a_0^2 <= 1e5 on every lane, since
+        // b0 <= |pose - o|^2 + a_0^2.  Any other unit, or body, runs the
+        // clamped per-point form below.
+        constexpr float kCap = 1.0e5f;
+        const bool mirrored = p.shape_kind == kShapeMirroredAxis;
+        bool fast = false;
+        if (mirrored && sa2[3] == 0.0f) {
+            const float bound = fmaf(2.0f, fmaf(pose.x, pose.x, pose.y * pose.y), omax2) + ss[0];
+            fast = __ballot(!(bound <= kCap)) == 0;
+        }
+        if (fast) {
             const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
-            const float AM = sa2[3], DM = ss[3] - ss[0];
+            const float DM = -ss[0];
             const float aA0 = fabsf(A0), aA1 = fabsf(A1), aA2 = fabsf(A2);
             const float nA0 = -(A0 * A0), nA1 = -(A1 * A1), nA2 = -(A2 * A2);
             run([&](const float4 o) __attribute__((always_inline)) {
@@ -582,10 +595,10 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
                 const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
                 const float b1 = b0 + D1, b2 = b0 + D2;
-                const float hm = b0 + fmaf(AM, pu, DM);
+                const float hm = b0 + DM;
                 const float apu = fabsf(pu);
                 const float g = fminf(fminf(fmaf(-aA0, apu, b0), fmaf(-aA1, apu, b1)),
-                                      fminf(fminf(fmaf(-aA2, apu, b2), hm), (kCap + gmin) - b0));
+                                      fminf(fmaf(-aA2, apu, b2), hm));
                 const float pu2 = pu * pu;
                 const float q0 = fmaf(b0, b0, nA0 * pu2), q1 = fmaf(b1, b1, nA1 * pu2);
                 const float q2 = fmaf(b2, b2, nA2 * pu2);
@@ -604,13 +617,17 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
                 half += f;
             });
         } else {
+            // (on the mirrored-axis tile o.z carries the a_0^2 offset)
+            float ssx[PM];
+#pragma unroll
+            for (int i = 0; i < PM; ++i) ssx[i] = mirrored ? ss[i] - ss[0] : ss[i];
             run([&](const float4 o) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
                 const float ee = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
                 float h[PM];
 #pragma unroll
-                for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ss[i]), eps);
+                for (int i = 0; i < PM; ++i) h[i] = clamp_h(ee + fmaf(sa2[i], pu, ssx[i]), eps);
                 reciprocal_sum<PM>(h, acc, acc2);
             });
         }
@@ -770,16 +787,20 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 
     // ---- staging: local frame centred on the start position ----
     const double ox = (double)xs.v[0], oy = (double)xs.v[1];
+    float omax_mine = 0.0f;     // this thread's largest |o|^2 (local frame), for the barrier's cap bound
+    float omax2 = 0.0f;         // 2 max_j |o_j|^2, known from the first stage on
     {
         // the vehicle's layout form and the quadrotor's mirrored-axis form
         // offset |e|^2 - r^2 by |s_0|^2 (third word); the fourth word keeps
-        // -r^2 for the start and goal poses' barrier
+        // -r^2
         const bool offset = PT != 0 && (MODEL == MPPI_CAR || p.shape_kind == kShapeMirroredAxis);
         const double s00 = (double)p.shape[0][0], s01 = (double)p.shape[0][1];
         const double d0 = offset ? s00 * s00 + s01 * s01 : 0.0;
         for (int j = tid; j < J; j += kRollBlock) {
             const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
-            L.obs[j] = make_float4((float)(cx - ox), (float)(cy - oy), (float)(d0 - r * r), (float)(-(r * r)));
+            const float4 o = make_float4((float)(cx - ox), (float)(cy - oy), (float)(d0 - r * r), (float)(-(r * r)));
+            L.obs[j] = o;
+            if constexpr (PT == 7) omax_mine = fmaxf(omax_mine, fmaf(o.x, o.x, o.y * o.y));
         }
     }
     if (tid < 8) L.work[tid] = 0;
@@ -991,7 +1012,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
                 for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
                 if (sp == 0 && item < items) bv[item] = part;
             } else {
-                if (item < all) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg);
+                if (item < all) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, omax2);
                 for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
                 if (sp == 0 && item < all) bv[item] = part;
             }
@@ -1015,6 +1036,11 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         }
     };
 
+    // the largest |o|^2 over the obstacles (work[7] was cleared before the
+    // staging barrier; non-negative floats order as their bit patterns)
+    if constexpr (PT == 7) {
+        if (omax_mine > 0.0f) atomicMax(&L.work[7], __float_as_int(omax_mine));
+    }
     // The first chunk's inputs, on the upper half of the workgroup, from the
     // words drawn at entry (and drawn here for any item beyond two per thread).
     if (j0 >= 0) {
@@ -1025,6 +1051,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             store_input(L.in, idx, idx / S, idx & (S - 1), noise_at(tile * S + (idx & (S - 1)), idx / S));
     }
     lds_barrier();
+    if constexpr (PT == 7) omax2 = 2.0f * __int_as_float(L.work[7]);
     // (the SIMD counts are final: the barriers since have synchronised)
     if constexpr (SC) {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));

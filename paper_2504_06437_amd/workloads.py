@@ -34,8 +34,10 @@ import numpy as np
 MODEL_DIMS = {"quad6": 6, "quad5": 5, "car": 4}
 
 # Shape points (body frame: along the heading, normal to it).
-# Quadrotor: 7 points evenly spaced on the 0.4 m frame, both propellers at the ends.
-QUAD_SHAPE = [[-0.2 + 0.4 * i / 6.0, 0.0] for i in range(7)]
+# Quadrotor: 7 points evenly spaced on the 0.4 m frame, both propellers at the
+# ends (written as 0.4 (i - 3) / 6, so the middle point is exactly the centre
+# and the pairs are exact mirrors).
+QUAD_SHAPE = [[0.4 * (i - 3) / 6.0, 0.0] for i in range(7)]
 # Vehicle: corners and side midpoints of a 4 m x 3 m rectangle.
 CAR_SHAPE = [[2.0, 1.5], [2.0, -1.5], [-2.0, 1.5], [-2.0, -1.5],
              [2.0, 0.0], [-2.0, 0.0], [0.0, 1.5], [0.0, -1.5]]
