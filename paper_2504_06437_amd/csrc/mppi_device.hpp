@@ -542,29 +542,39 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         constexpr float kCap = 2.0e4f;
         const float AA = ss[4], BB = ss[6];
         const float cu = sa2[0] * cs, su = sa2[0] * sn, cv = sb2[0] * cs, sv = sb2[0] * sn;
-        run([&](const float4 o) __attribute__((always_inline)) {
-            const float ex = pose.x - o.x, ey = pose.y - o.y;
-            const float C = fmaf(ex, ex, fmaf(ey, ey, o.z));
-            const float Pu = fmaf(ex, cu, ey * su), Qv = fmaf(ey, cv, -ex * sv);
-            const float X1 = C + Pu, X2 = C - Pu, X3 = C - BB, X4 = C - AA;
-            const float aP = fabsf(Pu), aQ = fabsf(Qv);
-            const float g = fminf(fminf(C - aP - aQ, X3 - aP), fminf(X4 - aQ, (kCap + gmin) - C));
-            const float P2 = Pu * Pu, Q2 = Qv * Qv;
-            const float q1 = fmaf(X1, X1, -Q2), q2 = fmaf(X2, X2, -Q2);
-            const float q3 = fmaf(X3, X3, -P2), q4 = fmaf(X4, X4, -Q2);
-            const float n12 = fmaf(X1, q2, X2 * q1), d12 = q1 * q2;
-            const float n34 = fmaf(X3, q4, X4 * q3), d34 = q3 * q4;
-            float f = fmaf(n12, d34, n34 * d12) * __builtin_amdgcn_rcpf(d12 * d34);
-            // (a wave-uniform branch: the clamped form only when a lane needs it)
-            if (__ballot(g < gmin)) {
-                float h[8] = {X1 + Qv, X1 - Qv, X2 + Qv, X2 - Qv, X1 - BB, X2 - BB, X4 + Qv, X4 - Qv};
+        // NOCAP: C <= |pose - o|^2 + a^2 + b^2 <= 2 |pose|^2 + 2 max_j |o_j|^2 +
+        // a^2 + b^2 is below the cap on every lane of the unit, so no obstacle
+        // needs the cap term in the guard
+        auto body = [&](auto nocap_tag) __attribute__((always_inline)) {
+            constexpr bool NOCAP = decltype(nocap_tag)::value;
+            run([&](const float4 o) __attribute__((always_inline)) {
+                const float ex = pose.x - o.x, ey = pose.y - o.y;
+                const float C = fmaf(ex, ex, fmaf(ey, ey, o.z));
+                const float Pu = fmaf(ex, cu, ey * su), Qv = fmaf(ey, cv, -ex * sv);
+                const float X1 = C + Pu, X2 = C - Pu, X3 = C - BB, X4 = C - AA;
+                const float aP = fabsf(Pu), aQ = fabsf(Qv);
+                const float g = NOCAP ? fminf(fminf(C - aP - aQ, X3 - aP), X4 - aQ)
+                                      : fminf(fminf(C - aP - aQ, X3 - aP), fminf(X4 - aQ, (kCap + gmin) - C));
+                const float P2 = Pu * Pu, Q2 = Qv * Qv;
+                const float q1 = fmaf(X1, X1, -Q2), q2 = fmaf(X2, X2, -Q2);
+                const float q3 = fmaf(X3, X3, -P2), q4 = fmaf(X4, X4, -Q2);
+                const float n12 = fmaf(X1, q2, X2 * q1), d12 = q1 * q2;
+                const float n34 = fmaf(X3, q4, X4 * q3), d34 = q3 * q4;
+                float f = fmaf(n12, d34, n34 * d12) * __builtin_amdgcn_rcpf(d12 * d34);
+                // (a wave-uniform branch: the clamped form only when a lane needs it)
+                if (__ballot(g < gmin)) {
+                    float h[8] = {X1 + Qv, X1 - Qv, X2 + Qv, X2 - Qv, X1 - BB, X2 - BB, X4 + Qv, X4 - Qv};
 #pragma unroll
-                for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
-                const float slow = 0.5f * reciprocal_total<8>(h);
-                f = g >= gmin ? f : slow;
-            }
-            half += f;
-        });
+                    for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
+                    const float slow = 0.5f * reciprocal_total<8>(h);
+                    f = g >= gmin ? f : slow;
+                }
+                half += f;
+            });
+        };
+        const float bound = fmaf(2.0f, fmaf(pose.x, pose.x, pose.y * pose.y), omax2) + ss[0];
+        if (__ballot(!(bound <= kCap)) == 0) body(std::true_type{});
+        else body(std::false_type{});
     } else if constexpr (PT != 0) {
         static_assert(PT == 7, "quadrotor layout: 7 points");
         // The mirrored-axis form: a_{6-i} = -a_i, and |a_0| is the largest
@@ -800,7 +810,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             const double cx = (double)p.obs[3 * j], cy = (double)p.obs[3 * j + 1], r = (double)p.obs[3 * j + 2];
             const float4 o = make_float4((float)(cx - ox), (float)(cy - oy), (float)(d0 - r * r), (float)(-(r * r)));
             L.obs[j] = o;
-            if constexpr (PT == 7) omax_mine = fmaxf(omax_mine, fmaf(o.x, o.x, o.y * o.y));
+            if constexpr (PT != 0) omax_mine = fmaxf(omax_mine, fmaf(o.x, o.x, o.y * o.y));
         }
     }
     if (tid < 8) L.work[tid] = 0;
@@ -1038,7 +1048,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
 
     // the largest |o|^2 over the obstacles (work[7] was cleared before the
     // staging barrier; non-negative floats order as their bit patterns)
-    if constexpr (PT == 7) {
+    if constexpr (PT != 0) {
         if (omax_mine > 0.0f) atomicMax(&L.work[7], __float_as_int(omax_mine));
     }
     // The first chunk's inputs, on the upper half of the workgroup, from the
@@ -1051,7 +1061,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
             store_input(L.in, idx, idx / S, idx & (S - 1), noise_at(tile * S + (idx & (S - 1)), idx / S));
     }
     lds_barrier();
-    if constexpr (PT == 7) omax2 = 2.0f * __int_as_float(L.work[7]);
+    if constexpr (PT != 0) omax2 = 2.0f * __int_as_float(L.work[7]);
     // (the SIMD counts are final: the barriers since have synchronised)
     if constexpr (SC) {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
