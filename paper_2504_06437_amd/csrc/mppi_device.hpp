@@ -598,31 +598,33 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         if (fast) {
             const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
             const float DM = -ss[0];
-            const float aA0 = fabsf(A0), aA1 = fabsf(A1), aA2 = fabsf(A2);
             const float nA0 = -(A0 * A0), nA1 = -(A1 * A1), nA2 = -(A2 * A2);
+            // The guard reads the fraction itself: h_m = b0 - a_0^2 is the
+            // smallest c_i, so h_m > 0 and q_i = (c_i - d_i)(c_i + d_i) > 0 put
+            // every h above 0; then f = (1/2) sum 1/h <= 1/(2 gmin) puts every
+            // h at or above gmin.  (A NaN f fails the comparison.)
+            const float fcap = 0.5f / gmin;
             run([&](const float4 o) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
                 const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
                 const float b1 = b0 + D1, b2 = b0 + D2;
                 const float hm = b0 + DM;
-                const float apu = fabsf(pu);
-                const float g = fminf(fminf(fmaf(-aA0, apu, b0), fmaf(-aA1, apu, b1)),
-                                      fminf(fmaf(-aA2, apu, b2), hm));
                 const float pu2 = pu * pu;
                 const float q0 = fmaf(b0, b0, nA0 * pu2), q1 = fmaf(b1, b1, nA1 * pu2);
                 const float q2 = fmaf(b2, b2, nA2 * pu2);
                 const float n01 = fmaf(b0, q1, b1 * q0), d01 = q0 * q1;
                 const float n2m = fmaf(b2, hm, 0.5f * q2), d2m = q2 * hm;
                 float f = fmaf(n01, d2m, n2m * d01) * __builtin_amdgcn_rcpf(d01 * d2m);
+                const bool ok = fminf(fminf(q0, q1), fminf(q2, hm)) > 0.0f && f <= fcap;
                 // (a wave-uniform branch: the clamped form only when a lane needs it)
-                if (__ballot(g < gmin)) {
+                if (__ballot(!ok)) {
                     float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), hm,
                                   fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
 #pragma unroll
                     for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
                     const float slow = 0.5f * reciprocal_total<7>(h);
-                    f = g >= gmin ? f : slow;
+                    f = ok ? f : slow;
                 }
                 half += f;
             });
