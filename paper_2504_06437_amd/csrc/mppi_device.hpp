@@ -603,22 +603,25 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             // smallest c_i, so h_m > 0 and q_i = (c_i - d_i)(c_i + d_i) > 0 put
             // every h above 0; then f = (1/2) sum 1/h <= 1/(2 gmin) puts every
             // h at or above gmin.  (A NaN f fails the comparison.)
-            const float fcap = 0.5f / gmin;
+            // (the middle point enters as hd = 2 h_m, so that pair 2 and the
+            // middle point meet as b2/q2 + 1/hd = (b2 hd + q2)/(q2 hd))
+            const float fcap = 0.5f / gmin, DM2 = 2.0f * DM;
             run([&](const float4 o) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
                 const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
                 const float pu = fmaf(ex, cs, ey * sn);
                 const float b1 = b0 + D1, b2 = b0 + D2;
-                const float hm = b0 + DM;
+                const float hd = fmaf(2.0f, b0, DM2);
                 const float pu2 = pu * pu;
                 const float q0 = fmaf(b0, b0, nA0 * pu2), q1 = fmaf(b1, b1, nA1 * pu2);
                 const float q2 = fmaf(b2, b2, nA2 * pu2);
                 const float n01 = fmaf(b0, q1, b1 * q0), d01 = q0 * q1;
-                const float n2m = fmaf(b2, hm, 0.5f * q2), d2m = q2 * hm;
+                const float n2m = fmaf(b2, hd, q2), d2m = q2 * hd;
                 float f = fmaf(n01, d2m, n2m * d01) * __builtin_amdgcn_rcpf(d01 * d2m);
-                const bool ok = fminf(fminf(q0, q1), fminf(q2, hm)) > 0.0f && f <= fcap;
+                const bool ok = fminf(fminf(q0, q1), fminf(q2, hd)) > 0.0f && f <= fcap;
                 // (a wave-uniform branch: the clamped form only when a lane needs it)
                 if (__ballot(!ok)) {
+                    const float hm = b0 + DM;
                     float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), hm,
                                   fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
 #pragma unroll
