@@ -50,6 +50,7 @@ from paper_2504_06437_amd import workloads as W  # noqa: E402
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
+CUS, XCDS = 256, 8                    # MI355X: compute units, and the dies (XCDs) they sit on
 METRIC = "rollout-steps/sec (K·T) and p50/p99 control-step latency, batched vs plain"
 # kernel durations of the shorter legs come from HIP events around every
 # PROFILE_EVERY-th iteration (the events of one iteration add a few
@@ -544,6 +545,24 @@ def _pmc_mean(csv_dir: str, counter: str, kernel_substr: str):
     return sum(vals) / len(vals), len(vals), [top]
 
 
+def _pmc_duration_s(csv_dir: str, kernel_substr: str, name: str) -> float:
+    """Mean start-to-end time of the dispatches of kernel `name` in a
+    rocprofv3 --pmc run (each counter row carries its dispatch's timestamps,
+    in ns)."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Kernel_Name") != name or kernel_substr not in name:
+                    continue
+                per[(f, row["Dispatch_Id"])] = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9
+    if not per:
+        raise SystemExit(f"no timestamps for {name!r} under {csv_dir}")
+    return sum(per.values()) / len(per)
+
+
 def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, workload, out_path):
     """HBM bytes per rollout launch from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by true bytes / counter reading of a plain copy."""
@@ -569,7 +588,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     return rec["rollout"][workload]
 
 
-def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
+def summarize_counters(sq1_dir, sq2_dir, workload, out_path, sq3_dir=None):
     """VALU use of the rollout from SQ counters (two rocprofv3 passes):
     instructions per wave, the waiting share, the transcendental share, and
     the executed FP32 FLOPs per launch, 64 lanes x (2 FMA + ADD + MUL) over
@@ -577,7 +596,14 @@ def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
     count wave instructions).  Also SQ_ACTIVE_INST_VALU / (SQ_WAVE_CYCLES /
     4), reported as a ratio: with four waves per SIMD living the whole
     launch it would be the SIMD's VALU busy fraction, but on gfx950 it
-    exceeds 1, so the two counters are not in the units that reading needs."""
+    exceeds 1, so the two counters are not in the units that reading needs.
+
+    An optional third pass gives the clock: GRBM_GUI_ACTIVE (summed over the
+    XCDs, so divided by their number) over the dispatch's own duration is
+    the clock the launch ran at, and SQ_INSTS_VALU over the SIMDs and those
+    cycles is the VALU instructions each SIMD issued per cycle.  It also
+    records SQ_VALU_MFMA_BUSY_CYCLES, which is 0 for a kernel that issues no
+    matrix instruction."""
     act, n, names = _pmc_mean(sq1_dir, "SQ_ACTIVE_INST_VALU", "k_rollout")
     wcyc, _, _ = _pmc_mean(sq1_dir, "SQ_WAVE_CYCLES", "k_rollout")
     waves, _, _ = _pmc_mean(sq1_dir, "SQ_WAVES", "k_rollout")
@@ -597,6 +623,13 @@ def summarize_counters(sq1_dir, sq2_dir, workload, out_path):
                   "executed_flops_per_launch": 64.0 * (2.0 * fma + add + mul)})
     except SystemExit:
         pass
+    if sq3_dir:
+        gui, _, names3 = _pmc_mean(sq3_dir, "GRBM_GUI_ACTIVE", "k_rollout")
+        mfma, _, _ = _pmc_mean(sq3_dir, "SQ_VALU_MFMA_BUSY_CYCLES", "k_rollout")
+        dur = _pmc_duration_s(sq3_dir, "k_rollout", names3[0])
+        cycles = gui / XCDS
+        r.update({"grbm_gui_active_per_xcd": cycles, "pmc_dispatch_s": dur, "clock_ghz": cycles / dur / 1e9,
+                  "valu_insts_per_simd_cycle": insts / (CUS * 4) / cycles, "mfma_busy_cycles": mfma})
     rec.setdefault("rollout", {})[workload] = r
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -642,15 +675,20 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", type=int, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration)")
-    ap.add_argument("--summarize-counters", nargs=2, metavar=("SQ1", "SQ2"),
-                    help="rocprofv3 SQ counter folders -> profiles/counters.json (no GPU use)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="SQ",
+                    help="two or three rocprofv3 SQ counter folders (the third: GRBM_GUI_ACTIVE and "
+                         "SQ_VALU_MFMA_BUSY_CYCLES) -> profiles/counters.json (no GPU use)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders -> profiles/traffic.json (no GPU use)")
     ap.add_argument("--copy-bytes", type=int, default=256 << 20)
     args = ap.parse_args()
     if args.summarize_counters:
-        print(json.dumps(summarize_counters(*args.summarize_counters, workload_name(WORKLOADS[args.workload]()),
-                                            os.path.join(ROOT, "profiles", "counters.json")), indent=1))
+        d = args.summarize_counters
+        if len(d) not in (2, 3):
+            ap.error("--summarize-counters takes two or three folders")
+        print(json.dumps(summarize_counters(d[0], d[1], workload_name(WORKLOADS[args.workload]()),
+                                            os.path.join(ROOT, "profiles", "counters.json"),
+                                            d[2] if len(d) == 3 else None), indent=1))
         return
     if args.summarize_traffic:
         r = summarize_traffic(*args.summarize_traffic, args.copy_bytes, workload_name(WORKLOADS[args.workload]()),

@@ -85,6 +85,20 @@ def test_counter_summary(tmp_path, monkeypatch):
     assert r["valu_insts_per_wave"] == pytest.approx(300.0)
     assert r["wait_frac"] == pytest.approx(0.5) and r["trans_share"] == pytest.approx(0.05)
     assert r["executed_flops_per_launch"] == pytest.approx(64 * 1300.0)
+    # the third pass: GRBM_GUI_ACTIVE summed over the 8 XCDs, 2.0e6 cycles
+    # each, over a 1 ms dispatch is a 2 GHz clock; 1200 VALU instructions
+    # over 1024 SIMDs and those cycles; no matrix-core cycles
+    sq3 = tmp_path / "sq3"
+    os.makedirs(sq3)
+    with open(sq3 / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(FIELDS + ["Start_Timestamp", "End_Timestamp"])
+        w.writerow([5, ROLLOUT, "GRBM_GUI_ACTIVE", 8 * 2.0e6, 1_000_000, 2_000_000])
+        w.writerow([5, ROLLOUT, "SQ_VALU_MFMA_BUSY_CYCLES", 0.0, 1_000_000, 2_000_000])
+    r3 = bench.summarize_counters(str(tmp_path / "sq1"), str(tmp_path / "sq2"), WORKLOAD, str(out), str(sq3))
+    assert r3["clock_ghz"] == pytest.approx(2.0) and r3["mfma_busy_cycles"] == 0.0
+    assert r3["valu_insts_per_simd_cycle"] == pytest.approx(1200.0 / 1024 / 2.0e6)
+    assert r3["executed_flops_per_launch"] == pytest.approx(64 * 1300.0)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
     os.replace(out, tmp_path / "profiles" / "counters.json")
