@@ -15,10 +15,14 @@ TOL_U = 1e-4
 DP = SENS_REACH
 
 
-def check_costs(Sg, Sr, sens, what=""):
+def check_costs(Sg, Sr, sens, what="", min_governed=0.5):
+    """Costs within 1e-4 relative plus the barrier's conditioning; the
+    relative term must govern for at least `min_governed` of the samples
+    (lower only where every sample passes within centimetres of an
+    obstacle, so that the conditioning governs by construction)."""
     base = TOL_S * np.maximum(np.abs(Sr), 1.0)
     cond = DP * sens
-    assert np.mean(cond <= base) >= 0.5, f"{what}: the relative bound governs only {np.mean(cond <= base):.2f}"
+    assert np.mean(cond <= base) >= min_governed, f"{what}: the relative bound governs only {np.mean(cond <= base):.2f}"
     d = np.abs(Sg - Sr)
     assert np.all(np.isfinite(Sg))
     assert np.all(d <= base + cond), f"{what} costs {np.max(d / (base + cond))} of the bound"
@@ -41,12 +45,12 @@ def check_weights(wg, wr, Sg, Sr, lam, what=""):
     assert np.max(np.abs(wg[big] - w_iso[big]) / w_iso[big]) <= 1e-5, f"{what} softmax in isolation"
 
 
-def check(gpu: dict, ref: dict, p: dict, S_e=1.0, what=""):
+def check(gpu: dict, ref: dict, p: dict, S_e=1.0, what="", min_governed=0.5):
     scale = math.sqrt(S_e) * np.asarray(p["sigma"], dtype=np.float64)
     if "du" in gpu:
         d = np.abs(gpu["du"] - ref["du"])
         assert np.all(d <= 1e-5 * np.abs(ref["du"]) + 1e-6 * scale + 1e-30), f"{what} noise {d.max()}"
-    check_costs(gpu["S"], ref["S"], ref["sens"], what)
+    check_costs(gpu["S"], ref["S"], ref["sens"], what, min_governed)
     check_weights(gpu["w"], ref["w"], gpu["S"], ref["S"], p["lambda"], what)
     for key in ("Ustar", "Unext"):
         d = np.abs(gpu[key] - ref[key])

@@ -47,7 +47,7 @@ def _world(wl):
     return oracle.World.from_workload(wl)
 
 
-def _one_iteration(wl, S_e=1.0, **over):
+def _one_iteration(wl, S_e=1.0, min_governed=0.5, **over):
     c, p = _ctrl(wl, **over)
     if S_e != 1.0:
         c.set_exploration(S_e)
@@ -57,7 +57,7 @@ def _one_iteration(wl, S_e=1.0, **over):
     info = c.info()
     ref = oracle.step(f32_params(p), _world(wl), wl["x0"], st["U"], wl["x_ref"], np.float32(S_e), st["counter"])
     assert ref["status"] == 0 and info["status"] == 0
-    _check(g, ref, p, S_e, what=str(over))
+    _check(g, ref, p, S_e, what=str(over), min_governed=min_governed)
     c.close()
     return g, ref, info
 
@@ -122,6 +122,36 @@ def test_both_barrier_forms_match_oracle():
     assert _one_iteration(dict(wl, params=dict(wl["params"], shape=rect)))[2]["barrier_form"] == 1
     axis = [[-0.3, 0.0], [-0.2, 0.0], [-0.05, 0.0], [0.02, 0.0], [0.05, 0.0], [0.2, 0.0], [0.3, 0.0]]
     assert _one_iteration(dict(wq, params=dict(wq["params"], shape=axis)))[2]["barrier_form"] == 2
+
+
+def test_far_and_touching_obstacles_match_oracle():
+    """The layout forms' two guards.  An obstacle touching the start sends
+    some samples into it, where an h falls below h_eps: those waves take the
+    clamped per-point form for that obstacle.  An obstacle far from the
+    start (240 m for the quadrotor, 120 m for the vehicle, in the
+    iteration's local frame) lets the pair fractions' shared term pass its
+    cap, so no unit may drop the cap test: the vehicle tests it per
+    obstacle, the quadrotor's axis runs the clamped per-point form.  Each
+    case matches the oracle.  Every quadrotor sample passes within a few
+    centimetres of the touching obstacle, so there the barrier's
+    conditioning governs the cost bound for most samples (the case is here
+    for the guard's failure branch, not for the 1e-4 bar, which the
+    far-only case and the vehicle's cases hold)."""
+    q = W.quad_small(K=512, T=20, J=10)
+    x, y = float(q["x0"][0]), float(q["x0"][1])
+    near_q, far_q = [x + 0.45, y, 0.22], [x + 240.0, y, 0.5]
+    c = W.car(K=512, T=20, J=20)
+    x, y = float(c["x0"][0]), float(c["x0"][1])
+    d = 2.6 / math.sqrt(2.0)          # ahead of the vehicle, along its 45-degree heading
+    near_c, far_c = [x + d, y + d, 0.5], [x, y + 120.0, 0.5]
+    cases = ((q, [far_q], 2, 0.0, 0.5), (q, [near_q], 2, 0.02, 0.0), (q, [near_q, far_q], 2, 0.02, 0.0),
+             (c, [near_c], 1, 0.02, 0.5), (c, [near_c, far_c], 1, 0.02, 0.5))
+    for wl, extra, form, least_inside, governed in cases:
+        w = dict(wl, obstacles=np.vstack([wl["obstacles"], np.asarray(extra, dtype=np.float32)]))
+        _, ref, info = _one_iteration(w, min_governed=governed)
+        assert info["barrier_form"] == form
+        inside = np.mean(np.asarray(ref["clear"]) < wl["params"]["h_eps"])
+        assert least_inside <= inside < 0.5, inside
 
 
 def test_degenerate_and_largest_sizes_match_oracle():
