@@ -518,6 +518,51 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
         }
         if (sp < rem) body(ob[0]);
     };
+    // The same walk for a guarded fast form: fast(o, m) gives an obstacle's
+    // sum f and the smallest of the terms whose signs the guard tests, and
+    // the form is exact there when m > 0 and f <= fmax; slow(o) gives the
+    // clamped per-point sum.  Four obstacles an iteration share one
+    // wave-uniform test (the smallest m and the largest f of the four), so
+    // the loop takes no branch per obstacle; the sums are added in obstacle
+    // order either way.
+    auto run_guarded = [&](auto&& fast, auto&& slow, float fmax, float& sum) __attribute__((always_inline)) {
+        auto one = [&](const float4 o) __attribute__((always_inline)) {
+            float m;
+            float f = fast(o, m);
+            const bool ok = (m > 0.0f) & (f <= fmax);
+            if (__builtin_expect(__ballot(!ok) != 0, 0)) {
+                const float s = slow(o);
+                f = ok ? f : s;
+            }
+            sum += f;
+        };
+        const float4* ob = L.obs + sp;
+        int i = 0;
+        for (; i + 4 <= q; i += 4) {
+            const float4 o0 = ob[0], o1 = ob[js], o2 = ob[2 * js], o3 = ob[3 * js];
+            ob += 4 * js;
+            float m0, m1, m2, m3;
+            float f0 = fast(o0, m0), f1 = fast(o1, m1), f2 = fast(o2, m2), f3 = fast(o3, m3);
+            const bool ok = (fminf(fminf(m0, m1), fminf(m2, m3)) > 0.0f) & (fmaxf(fmaxf(f0, f1), fmaxf(f2, f3)) <= fmax);
+            if (__builtin_expect(__ballot(!ok) != 0, 0)) {
+                const bool k0 = (m0 > 0.0f) & (f0 <= fmax), k1 = (m1 > 0.0f) & (f1 <= fmax);
+                const bool k2 = (m2 > 0.0f) & (f2 <= fmax), k3 = (m3 > 0.0f) & (f3 <= fmax);
+                if (__ballot(!k0)) { const float s = slow(o0); f0 = k0 ? f0 : s; }
+                if (__ballot(!k1)) { const float s = slow(o1); f1 = k1 ? f1 : s; }
+                if (__ballot(!k2)) { const float s = slow(o2); f2 = k2 ? f2 : s; }
+                if (__ballot(!k3)) { const float s = slow(o3); f3 = k3 ? f3 : s; }
+            }
+            sum += f0;
+            sum += f1;
+            sum += f2;
+            sum += f3;
+        }
+        for (; i < q; ++i) {
+            one(ob[0]);
+            ob += js;
+        }
+        if (sp < rem) one(ob[0]);
+    };
     // Pair fractions (the layout forms' fast path).  Two points whose h are
     // c + d and c - d give 1/(c+d) + 1/(c-d) = 2c/(c^2 - d^2); the bodies of
     // Sec. V split into such pairs (the vehicle's four, the quadrotor's three
@@ -562,7 +607,7 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
                 const float n34 = fmaf(X3, q4, X4 * q3), d34 = q3 * q4;
                 float f = fmaf(n12, d34, n34 * d12) * __builtin_amdgcn_rcpf(d12 * d34);
                 // (a wave-uniform branch: the clamped form only when a lane needs it)
-                if (__ballot(g < gmin)) {
+                if (__builtin_expect(__ballot(g < gmin) != 0, 0)) {
                     float h[8] = {X1 + Qv, X1 - Qv, X2 + Qv, X2 - Qv, X1 - BB, X2 - BB, X4 + Qv, X4 - Qv};
 #pragma unroll
                     for (int i = 0; i < 8; ++i) h[i] = clamp_h(h[i], eps);
@@ -596,9 +641,15 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             fast = __ballot(!(bound <= kCap)) == 0;
         }
         if (fast) {
-            const float A0 = sa2[0], A1 = sa2[1], A2 = sa2[2], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
+            const float A0 = sa2[0], D1 = ss[1] - ss[0], D2 = ss[2] - ss[0];
             const float DM = -ss[0];
-            const float nA0 = -(A0 * A0), nA1 = -(A1 * A1), nA2 = -(A2 * A2);
+            // The heading projection enters scaled by A0 = 2 a_0: w = A0 e.u,
+            // so pair 0's q is b0^2 - w^2 with no coefficient, and pair i's
+            // is b_i^2 - (A_i / A0)^2 w^2.  (A0 = 0 only for a body whose
+            // points all sit at its centre: then every A_i is 0.)
+            const float R1 = A0 != 0.0f ? sa2[1] / A0 : 0.0f, R2 = A0 != 0.0f ? sa2[2] / A0 : 0.0f;
+            const float nK1 = -(R1 * R1), nK2 = -(R2 * R2);
+            const float csw = A0 * cs, snw = A0 * sn;
             // The guard reads the fraction itself: h_m = b0 - a_0^2 is the
             // smallest c_i, so h_m > 0 and q_i = (c_i - d_i)(c_i + d_i) > 0 put
             // every h above 0; then f = (1/2) sum 1/h <= 1/(2 gmin) puts every
@@ -606,31 +657,31 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             // (the middle point enters as hd = 2 h_m, so that pair 2 and the
             // middle point meet as b2/q2 + 1/hd = (b2 hd + q2)/(q2 hd))
             const float fcap = 0.5f / gmin, DM2 = 2.0f * DM;
-            run([&](const float4 o) __attribute__((always_inline)) {
+            auto fast_sum = [&](const float4 o, float& m) __attribute__((always_inline)) {
                 const float ex = pose.x - o.x, ey = pose.y - o.y;
                 const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
-                const float pu = fmaf(ex, cs, ey * sn);
+                const float w = fmaf(ex, csw, ey * snw);
                 const float b1 = b0 + D1, b2 = b0 + D2;
                 const float hd = fmaf(2.0f, b0, DM2);
-                const float pu2 = pu * pu;
-                const float q0 = fmaf(b0, b0, nA0 * pu2), q1 = fmaf(b1, b1, nA1 * pu2);
-                const float q2 = fmaf(b2, b2, nA2 * pu2);
+                const float w2 = w * w;
+                const float q0 = fmaf(b0, b0, -w2), q1 = fmaf(b1, b1, nK1 * w2);
+                const float q2 = fmaf(b2, b2, nK2 * w2);
                 const float n01 = fmaf(b0, q1, b1 * q0), d01 = q0 * q1;
                 const float n2m = fmaf(b2, hd, q2), d2m = q2 * hd;
-                float f = fmaf(n01, d2m, n2m * d01) * __builtin_amdgcn_rcpf(d01 * d2m);
-                const bool ok = fminf(fminf(q0, q1), fminf(q2, hd)) > 0.0f && f <= fcap;
-                // (a wave-uniform branch: the clamped form only when a lane needs it)
-                if (__ballot(!ok)) {
-                    const float hm = b0 + DM;
-                    float h[7] = {fmaf(A0, pu, b0), fmaf(A1, pu, b1), fmaf(A2, pu, b2), hm,
-                                  fmaf(-A2, pu, b2), fmaf(-A1, pu, b1), fmaf(-A0, pu, b0)};
+                m = fminf(fminf(q0, q1), fminf(q2, hd));
+                return fmaf(n01, d2m, n2m * d01) * __builtin_amdgcn_rcpf(d01 * d2m);
+            };
+            auto clamped_sum = [&](const float4 o) __attribute__((always_inline)) {
+                const float ex = pose.x - o.x, ey = pose.y - o.y;
+                const float b0 = fmaf(ex, ex, fmaf(ey, ey, o.z));
+                const float w = fmaf(ex, csw, ey * snw);
+                const float b1 = b0 + D1, b2 = b0 + D2, hm = b0 + DM;
+                float h[7] = {b0 + w, fmaf(R1, w, b1), fmaf(R2, w, b2), hm, fmaf(-R2, w, b2), fmaf(-R1, w, b1), b0 - w};
 #pragma unroll
-                    for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
-                    const float slow = 0.5f * reciprocal_total<7>(h);
-                    f = ok ? f : slow;
-                }
-                half += f;
-            });
+                for (int i = 0; i < 7; ++i) h[i] = clamp_h(h[i], eps);
+                return 0.5f * reciprocal_total<7>(h);
+            };
+            run_guarded(fast_sum, clamped_sum, fcap, half);
         } else {
             // (on the mirrored-axis tile o.z carries the a_0^2 offset)
             float ssx[PM];
