@@ -489,7 +489,7 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 // The runtime-P tile takes any shape: h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2
 // with d_i the rotated offset, one add and two FMAs a pair.
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
-template <int MODEL, int PT>
+template <int MODEL, int PT, bool GROUPED>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
                                                     const float* sb2, const float* ss, float4 pose, int sp, int lg,
                                                     float omax2)
@@ -536,6 +536,11 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             }
             sum += f;
         };
+        // (the batched kernel, short of registers, keeps a test per obstacle)
+        if constexpr (!GROUPED) {
+            run(one);
+            return;
+        }
         const float4* ob = L.obs + sp;
         int i = 0;
         for (; i + 4 <= q; i += 4) {
@@ -1078,7 +1083,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
                 for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
                 if (sp == 0 && item < items) bv[item] = part;
             } else {
-                if (item < all) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, omax2);
+                if (item < all) part = fused_barrier_pose<MODEL, PT, SC>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, omax2);
                 for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
                 if (sp == 0 && item < all) bv[item] = part;
             }
