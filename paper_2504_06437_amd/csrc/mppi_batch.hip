@@ -89,7 +89,8 @@ struct mppi_batch {
             const DevParams& p = params[c];
             const double cost = tile_cost(p.spt, p.K, p.T, p.P, p.J);
             const size_t lds = tile_lds_bytes(p.J, p.T, p.n, p.spt);
-            for (int t = 0; t < p.tiles; ++t) work.push_back({cost, p.model, lds, BatchUnit{c, t}});
+            const int group = batch_group(p);
+            for (int t = 0; t < p.tiles; ++t) work.push_back({cost, group, lds, BatchUnit{c, t}});
             for (int r = 0; r < 2 * p.T; r += kUpdBlock / kWave) rows.push_back(RowUnit{c, r});
             if (p.adaptive) {
                 exp_ids.push_back(c);
@@ -168,8 +169,8 @@ extern "C" int mppi_batch_create(mppi_t* const* ctrls, int32_t n, const mppi_dev
     }
     for (mppi_ctrl* c : b->ctrls)
         if (!st) st = c->sync();
-    if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2 * kModels), "hipMalloc queue");
-    if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2 * kModels), "queue init");
+    if (!st) st = b->hip(hipMalloc(&b->d_queue, sizeof(uint32_t) * 2 * kBatchGroups), "hipMalloc queue");
+    if (!st) st = b->hip(hipMemset(b->d_queue, 0, sizeof(uint32_t) * 2 * kBatchGroups), "queue init");
     if (!st) st = b->hip(hipMalloc(&b->d_in, sizeof(BatchIn) * n), "hipMalloc inputs");
     if (!st) st = b->hip(hipHostMalloc(reinterpret_cast<void**>(&b->h_in), sizeof(BatchIn) * n, 0), "hipHostMalloc inputs");
     if (!st) {

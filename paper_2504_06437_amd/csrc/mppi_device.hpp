@@ -1457,6 +1457,41 @@ __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* _
 }
 
 
+// The same over the units of one layout-form tile size (the paper's bodies,
+// no costmap, no indicator): the tile of the standalone kernel, its barrier
+// units shared out by SIMD.
+template <int MODEL, int S>
+__global__ __launch_bounds__(kRollBlock) void k_batch_rollout_layout(const DevParams* __restrict__ ps,
+                                                                     const BatchUnit* __restrict__ units, int nunits,
+                                                                     const BatchIn* __restrict__ in, uint32_t* queue)
+{
+    constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_unit;
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int u = s_unit;
+        __syncthreads();
+        if (u >= nunits) break;
+        const BatchUnit bu = units[u];
+        const DevParams& p = ps[bu.ctrl];
+        X0 xs;
+#pragma unroll
+        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
+        xs.parity = in[bu.ctrl].parity;
+        rollout_tile<MODEL, S, PD, true, false, false>(p, bu.tile, xs, smem);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1u) {
+            queue[0] = 0u;
+            queue[1] = 0u;
+        }
+    }
+}
+
 template <int MODEL, int S>
 hipError_t launch_rollout_ms(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s)
 {

@@ -123,24 +123,33 @@ struct BatchUnit {
 
 constexpr int kModels = 3;          // MPPI_QUAD6, MPPI_QUAD5, MPPI_CAR
 
-// The rollout units of a batched launch, grouped by model: one persistent
-// kernel per model present (a kernel that holds every model's tile needs more
-// registers and runs each of them slower).  Group m is units
-// [begin[m], begin[m] + count[m]) of the list, longest first; lds[m] is the
-// dynamic LDS its kernel needs and work[m] the sum of its units' estimates.
-// The queue of group m is words 2m and 2m + 1.
+// Kernels of the batched rollout, per model: one per tile size for the
+// layout-form tiles of the paper's bodies with neither costmap nor indicator
+// (the shape of most controllers; each kernel holds one tile and has the
+// registers of the standalone kernel), and one holding every other tile.
+constexpr int kTileSizes = 5;       // S = 16, 32, 64, 128, 256
+constexpr int kBatchKeys = kTileSizes + 1;
+constexpr int kBatchGroups = kModels * kBatchKeys;
+
+// The rollout units of a batched launch, grouped by kernel: one persistent
+// launch per group present (a kernel that holds many tiles needs more
+// registers and runs each of them slower).  Group g (model g / kBatchKeys,
+// kernel g % kBatchKeys) is units [begin[g], begin[g] + count[g]) of the
+// list, longest first; lds[g] is the dynamic LDS its kernel needs and
+// work[g] the sum of its units' estimates.  The queue of group g is words
+// 2g and 2g + 1.
 struct UnitGroups {
-    int begin[kModels];
-    int count[kModels];
-    size_t lds[kModels];
-    double work[kModels];
+    int begin[kBatchGroups];
+    int count[kBatchGroups];
+    size_t lds[kBatchGroups];
+    double work[kBatchGroups];
 };
 
-// A rollout unit before grouping, with its model, its estimated work and the
+// A rollout unit before grouping, with its group, its estimated work and the
 // dynamic LDS of its tile.
 struct BatchWork {
     double cost;
-    int32_t model;
+    int32_t group;
     size_t lds;
     BatchUnit unit;
 };
@@ -318,12 +327,14 @@ inline size_t tile_lds_bytes(int J, int T, int n, int S)
 // Kernel launchers (mppi_kernels.hip).  The rollout kernels of each model
 // live in their own unit (mppi_rollout_<model>.hip).
 using BatchRolloutKernel = void (*)(const DevParams*, const BatchUnit*, int, const BatchIn*, uint32_t*);
+// The batched rollout kernel of `key` (0..kTileSizes-1: the layout-form tile
+// of S = 16 << key; kTileSizes: every other tile) of each model.
 hipError_t launch_rollout_quad6(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_rollout_quad5(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_rollout_car(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
-BatchRolloutKernel batch_rollout_kernel_quad6();
-BatchRolloutKernel batch_rollout_kernel_quad5();
-BatchRolloutKernel batch_rollout_kernel_car();
+BatchRolloutKernel batch_rollout_kernel_quad6(int key);
+BatchRolloutKernel batch_rollout_kernel_quad5(int key);
+BatchRolloutKernel batch_rollout_kernel_car(int key);
 hipError_t launch_rollout(const DevParams& p, const StepArgs& a, hipStream_t s);
 hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s);
 // One persistent rollout launch per group, in order of decreasing work, each
@@ -338,7 +349,9 @@ hipError_t launch_batch_explore(const DevParams* d_params, const int32_t* d_ids,
 hipError_t launch_weights(const DevParams& p, double* d_w, hipStream_t s);
 hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d_words, hipStream_t s);
 hipError_t launch_sdf_cells(const float* sdf, int W, int H, float4* out, hipStream_t s);
-int batch_rollout_blocks_per_cu(int model, size_t lds);
+int batch_rollout_blocks_per_cu(int group, size_t lds);
+// The batch group of a controller's tiles (see UnitGroups).
+int batch_group(const DevParams& p);
 bool tile_samples_supported(int S);
 
 }  // namespace dbas

@@ -352,12 +352,13 @@ hipError_t launch_update(const DevParams& p, const StepArgs& a, hipStream_t s)
 
 namespace {
 
-BatchRolloutKernel batch_rollout_kernel(int model)
+BatchRolloutKernel batch_rollout_kernel(int group)
 {
-    switch (model) {
-    case MPPI_QUAD6: return batch_rollout_kernel_quad6();
-    case MPPI_QUAD5: return batch_rollout_kernel_quad5();
-    default: return batch_rollout_kernel_car();
+    const int key = group % kBatchKeys;
+    switch (group / kBatchKeys) {
+    case MPPI_QUAD6: return batch_rollout_kernel_quad6(key);
+    case MPPI_QUAD5: return batch_rollout_kernel_quad5(key);
+    default: return batch_rollout_kernel_car(key);
     }
 }
 
@@ -366,19 +367,19 @@ BatchRolloutKernel batch_rollout_kernel(int model)
 UnitGroups group_units(std::vector<BatchWork>& work, BatchUnit* out)
 {
     std::stable_sort(work.begin(), work.end(), [](const BatchWork& a, const BatchWork& b) {
-        return a.model != b.model ? a.model < b.model : a.cost > b.cost;
+        return a.group != b.group ? a.group < b.group : a.cost > b.cost;
     });
     UnitGroups g{};
-    for (int m = 0; m < kModels; ++m) g.begin[m] = -1;
+    for (int m = 0; m < kBatchGroups; ++m) g.begin[m] = -1;
     for (size_t i = 0; i < work.size(); ++i) {
-        const int m = work[i].model;
+        const int m = work[i].group;
         if (g.begin[m] < 0) g.begin[m] = (int)i;
         ++g.count[m];
         g.work[m] += work[i].cost;
         if (work[i].lds > g.lds[m]) g.lds[m] = work[i].lds;
         out[i] = work[i].unit;
     }
-    for (int m = 0; m < kModels; ++m)
+    for (int m = 0; m < kBatchGroups; ++m)
         if (g.begin[m] < 0) g.begin[m] = 0;
     return g;
 }
@@ -386,9 +387,10 @@ UnitGroups group_units(std::vector<BatchWork>& work, BatchUnit* out)
 hipError_t launch_batch_rollouts(const DevParams* d_params, const BatchUnit* d_units, const UnitGroups& g,
                                  const BatchIn* d_in, uint32_t* d_queue, int cus, hipStream_t s)
 {
-    int order[kModels] = {0, 1, 2};
-    std::stable_sort(order, order + kModels, [&](int a, int b) { return g.work[a] > g.work[b]; });
-    for (int i = 0; i < kModels; ++i) {
+    int order[kBatchGroups];
+    for (int i = 0; i < kBatchGroups; ++i) order[i] = i;
+    std::stable_sort(order, order + kBatchGroups, [&](int a, int b) { return g.work[a] > g.work[b]; });
+    for (int i = 0; i < kBatchGroups; ++i) {
         const int m = order[i];
         if (g.count[m] == 0) continue;
         const int grid = std::max(1, std::min(g.count[m], cus * batch_rollout_blocks_per_cu(m, g.lds[m])));
@@ -440,10 +442,21 @@ hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d
     return hipGetLastError();
 }
 
-int batch_rollout_blocks_per_cu(int model, size_t lds)
+int batch_group(const DevParams& p)
+{
+    int key = kTileSizes;
+    if (p.cost_mode != MPPI_COST_INDICATOR && p.sdf == nullptr && p.P == fixed_points(p.model) &&
+        p.shape_kind != kShapeGeneral) {
+        for (int k = 0; k < kTileSizes; ++k)
+            if (p.spt == (16 << k)) key = k;
+    }
+    return p.model * kBatchKeys + key;
+}
+
+int batch_rollout_blocks_per_cu(int group, size_t lds)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_rollout_kernel(model), kRollBlock, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_rollout_kernel(group), kRollBlock, lds) !=
         hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;

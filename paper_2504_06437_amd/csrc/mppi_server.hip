@@ -231,7 +231,8 @@ size_t mppi_server::stage(Slot& sl, UnitGroups* groups, int* nrows_out, size_t* 
         for (int r = 0; r < 2 * q.T; r += kUpdBlock / kWave) rows[r_at++] = RowUnit{i, r};
         const double cost = tile_cost(q.spt, q.K, q.T, q.P, q.J);
         const size_t lds = tile_lds_bytes(q.J, q.T, q.n, q.spt);
-        for (int t = 0; t < q.tiles; ++t) work.push_back({cost, q.model, lds, BatchUnit{i, t}});
+        const int group = batch_group(q);
+        for (int t = 0; t < q.tiles; ++t) work.push_back({cost, group, lds, BatchUnit{i, t}});
         if (q.adaptive) {
             exp_ids[nexp++] = i;
             lds_exp = std::max(lds_exp, explore_lds_bytes(q.J, q.T));
@@ -381,8 +382,8 @@ extern "C" int mppi_server_create(const mppi_server_config* cfg, mppi_server_t**
     for (Slot& sl : s->slots) {
         if (e == hipSuccess) e = hipStreamCreate(&sl.stream);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_queue), sizeof(uint32_t) * 2 * kModels);
-        if (e == hipSuccess) e = hipMemset(sl.d_queue, 0, sizeof(uint32_t) * 2 * kModels);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.d_queue), sizeof(uint32_t) * 2 * kBatchGroups);
+        if (e == hipSuccess) e = hipMemset(sl.d_queue, 0, sizeof(uint32_t) * 2 * kBatchGroups);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {

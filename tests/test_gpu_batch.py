@@ -84,8 +84,9 @@ def test_batch_replays_follow_obstacle_changes():
 
 @pytest.mark.parametrize("models", [("quad6", "quad5", "car"), ("quad5",), ("car", "car")])
 def test_batch_groups_by_model(models):
-    """The batched rollout runs one persistent launch per model present, each
-    with its own queue; every controller still equals its standalone run, on
+    """The batched rollout runs one persistent launch per kernel group present
+    (model, and for the layout-form tiles the tile size), each with its own
+    queue; every controller still equals its standalone run, on
     replays too (each launch's queue is reset by its last workgroup), and a
     shape point count other than the model's default takes the runtime-P tile."""
     from paper_2504_06437_amd.controller import Batch
@@ -103,6 +104,33 @@ def test_batch_groups_by_model(models):
     mixed = [_make(wl) for wl in wls]
     batch = Batch(mixed)
     for _ in range(3):
+        u_b, sts = batch.step([wl["x0"] for wl in wls])
+        assert np.all(sts == 0)
+        for i, (a, m, wl) in enumerate(zip(alone, mixed, wls)):
+            np.testing.assert_array_equal(a.step(wl["x0"]), u_b[i])
+            np.testing.assert_array_equal(a.costs(), m.costs())
+    batch.close()
+    for c in alone + mixed:
+        c.close()
+
+
+def test_batch_kernels_by_tile_shape():
+    """Layout-form tiles without a costmap run in one batched kernel per
+    model and tile size, every other tile (a costmap, a runtime-P body) in
+    the model's general batched kernel: a batch holding each kind, at two
+    tile sizes, equals each controller stepped alone."""
+    from paper_2504_06437_amd.controller import Batch
+    rng = np.random.Generator(np.random.PCG64(41))
+    wls = [W.quad_large(K=700, T=12, J=40, cells=64),
+           W.mixed_controller(rng, 501, K=900, T=14, J=30, model="quad6"),
+           W.mixed_controller(rng, 502, K=400, T=9, J=25, model="car"),
+           W.mixed_controller(rng, 503, K=600, T=11, J=33, model="quad6")]
+    wls[3]["params"] = dict(wls[3]["params"], tile_samples=64)
+    wls[2]["params"] = dict(wls[2]["params"], shape=[[-1.0, 0.0], [0.0, 0.0], [1.0, 0.0]])
+    alone = [_make(wl) for wl in wls]
+    mixed = [_make(wl) for wl in wls]
+    batch = Batch(mixed)
+    for _ in range(2):
         u_b, sts = batch.step([wl["x0"] for wl in wls])
         assert np.all(sts == 0)
         for i, (a, m, wl) in enumerate(zip(alone, mixed, wls)):
