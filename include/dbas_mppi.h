@@ -335,10 +335,10 @@ int mppi_step_noalloc(const mppi_config* cfg, const mppi_problem* prob, int32_t 
 
 /* ------------------------------------------------------------------------ */
 /* Batched iteration: many controllers (any mix of models, K, T, J) stepped  */
-/* by one persistent kernel, captured once in a HIP graph.  Controllers stay */
-/* owned by the caller and must outlive the batch; each one's tile shape is   */
-/* its own (autotuned per model, K, T, J), so a controller's result is the    */
-/* same alone and in the batch.                                              */
+/* by persistent kernels (one per model and tile kind present), captured     */
+/* once in a HIP graph.  Controllers stay owned by the caller and must       */
+/* outlive the batch; each one's tile shape is its own (autotuned per model, */
+/* K, T, J), so a controller's result is the same alone and in the batch.    */
 /* ------------------------------------------------------------------------ */
 typedef struct mppi_batch mppi_batch_t;
 
