@@ -1048,8 +1048,8 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     // one unit short, when there is one, goes to the owner's SIMD), or,
     // should that SIMD have no pool wave, by the next one that has.  Within a
     // SIMD the pool waves take the class's units round-robin by slot; the
-    // owner waves take none.  Without SC (the batched kernel, where the
-    // extra state costs registers) every wave takes units from an LDS
+    // owner waves take none.  Without SC (the general batched kernel, where
+    // the extra state costs registers) every wave takes units from an LDS
     // counter.  Which wave computes a unit never changes its arithmetic.
     auto barrier_chunk = [&](int c) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
