@@ -117,15 +117,20 @@ def test_batch_groups_by_model(models):
 def test_batch_kernels_by_tile_shape():
     """Layout-form tiles without a costmap run in one batched kernel per
     model and tile size, every other tile (a costmap, a runtime-P body) in
-    the model's general batched kernel: a batch holding each kind, at two
-    tile sizes, equals each controller stepped alone."""
+    the model's general batched kernel: a batch holding each kind, at tile
+    sizes 64, 128, 256 and the tuned ones, equals each controller stepped
+    alone."""
     from paper_2504_06437_amd.controller import Batch
     rng = np.random.Generator(np.random.PCG64(41))
     wls = [W.quad_large(K=700, T=12, J=40, cells=64),
            W.mixed_controller(rng, 501, K=900, T=14, J=30, model="quad6"),
            W.mixed_controller(rng, 502, K=400, T=9, J=25, model="car"),
-           W.mixed_controller(rng, 503, K=600, T=11, J=33, model="quad6")]
+           W.mixed_controller(rng, 503, K=600, T=11, J=33, model="quad6"),
+           W.mixed_controller(rng, 504, K=700, T=10, J=28, model="car"),
+           W.mixed_controller(rng, 505, K=900, T=13, J=36, model="quad6")]
     wls[3]["params"] = dict(wls[3]["params"], tile_samples=64)
+    wls[4]["params"] = dict(wls[4]["params"], tile_samples=128)
+    wls[5]["params"] = dict(wls[5]["params"], tile_samples=256)
     wls[2]["params"] = dict(wls[2]["params"], shape=[[-1.0, 0.0], [0.0, 0.0], [1.0, 0.0]])
     alone = [_make(wl) for wl in wls]
     mixed = [_make(wl) for wl in wls]
