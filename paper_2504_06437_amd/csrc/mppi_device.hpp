@@ -1392,40 +1392,11 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
     rollout_tile<MODEL, S, PT, true, IND, MAP>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
 
-template <int MODEL, int S>
-__device__ __forceinline__ void dispatch_p(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
-{
-    constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    const bool map = p.sdf != nullptr;
-    if (p.cost_mode == MPPI_COST_INDICATOR) {
-        if (map) rollout_tile<MODEL, S, 0, false, true, true>(p, tile, xs, smem);
-        else rollout_tile<MODEL, S, 0, false, true, false>(p, tile, xs, smem);
-    } else if (p.P == PD && p.shape_kind != kShapeGeneral) {
-        if (map) rollout_tile<MODEL, S, PD, false, false, true>(p, tile, xs, smem);
-        else rollout_tile<MODEL, S, PD, false, false, false>(p, tile, xs, smem);
-    } else {
-        if (map) rollout_tile<MODEL, S, 0, false, false, true>(p, tile, xs, smem);
-        else rollout_tile<MODEL, S, 0, false, false, false>(p, tile, xs, smem);
-    }
-}
-
-template <int MODEL>
-__device__ __forceinline__ void dispatch_s(const DevParams& p, int tile, const X0& xs, unsigned char* smem)
-{
-    switch (p.spt) {
-    case 16: dispatch_p<MODEL, 16>(p, tile, xs, smem); break;
-    case 32: dispatch_p<MODEL, 32>(p, tile, xs, smem); break;
-    case 64: dispatch_p<MODEL, 64>(p, tile, xs, smem); break;
-    case 128: dispatch_p<MODEL, 128>(p, tile, xs, smem); break;
-    default: dispatch_p<MODEL, 256>(p, tile, xs, smem); break;
-    }
-}
-
 // Persistent rollout over a work list of (controller, tile) units of one
-// model, taken in list order (the host sorts it longest-first).  Every block
-// leaves the loop once the list is exhausted; the last block to leave resets
-// the queue.
-template <int MODEL>
+// tile shape, taken in list order (the host sorts it longest-first): the
+// tile of the standalone kernel of that shape.  Every block leaves the loop
+// once the list is exhausted; the last block to leave resets the queue.
+template <int MODEL, int S, int PT, bool IND, bool MAP>
 __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* __restrict__ ps,
                                                               const BatchUnit* __restrict__ units, int nunits,
                                                               const BatchIn* __restrict__ in, uint32_t* queue)
@@ -1444,7 +1415,7 @@ __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* _
 #pragma unroll
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
         xs.parity = in[bu.ctrl].parity;
-        dispatch_s<MODEL>(p, bu.tile, xs, smem);
+        rollout_tile<MODEL, S, PT, true, IND, MAP>(p, bu.tile, xs, smem);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -1456,39 +1427,33 @@ __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* _
     }
 }
 
-
-// The same over the units of one layout-form tile size (the paper's bodies,
-// no costmap, no indicator): the tile of the standalone kernel, its barrier
-// units shared out by SIMD.
+// The batched kernel of one model's `key` (kind key / kTileSizes: layout
+// form, runtime P, indicator, each without and with a costmap; tile size
+// 16 << key % kTileSizes).
 template <int MODEL, int S>
-__global__ __launch_bounds__(kRollBlock) void k_batch_rollout_layout(const DevParams* __restrict__ ps,
-                                                                     const BatchUnit* __restrict__ units, int nunits,
-                                                                     const BatchIn* __restrict__ in, uint32_t* queue)
+BatchRolloutKernel batch_kernel_of_kind(int kind)
 {
     constexpr int PD = MODEL == MPPI_CAR ? 8 : 7;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_unit;
-    for (;;) {
-        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&queue[0], 1u);
-        __syncthreads();
-        const int u = s_unit;
-        __syncthreads();
-        if (u >= nunits) break;
-        const BatchUnit bu = units[u];
-        const DevParams& p = ps[bu.ctrl];
-        X0 xs;
-#pragma unroll
-        for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
-        xs.parity = in[bu.ctrl].parity;
-        rollout_tile<MODEL, S, PD, true, false, false>(p, bu.tile, xs, smem);
-        __syncthreads();
+    switch (kind) {
+    case 0: return k_batch_rollout<MODEL, S, PD, false, false>;
+    case 1: return k_batch_rollout<MODEL, S, PD, false, true>;
+    case 2: return k_batch_rollout<MODEL, S, 0, false, false>;
+    case 3: return k_batch_rollout<MODEL, S, 0, false, true>;
+    case 4: return k_batch_rollout<MODEL, S, 0, true, false>;
+    default: return k_batch_rollout<MODEL, S, 0, true, true>;
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1u) {
-            queue[0] = 0u;
-            queue[1] = 0u;
-        }
+}
+
+template <int MODEL>
+BatchRolloutKernel batch_kernel_of(int key)
+{
+    const int kind = key / kTileSizes;
+    switch (key % kTileSizes) {
+    case 0: return batch_kernel_of_kind<MODEL, 16>(kind);
+    case 1: return batch_kernel_of_kind<MODEL, 32>(kind);
+    case 2: return batch_kernel_of_kind<MODEL, 64>(kind);
+    case 3: return batch_kernel_of_kind<MODEL, 128>(kind);
+    default: return batch_kernel_of_kind<MODEL, 256>(kind);
     }
 }
 

@@ -123,19 +123,20 @@ struct BatchUnit {
 
 constexpr int kModels = 3;          // MPPI_QUAD6, MPPI_QUAD5, MPPI_CAR
 
-// Kernels of the batched rollout, per model: one per tile size for the
-// layout-form tiles of the paper's bodies with neither costmap nor indicator
-// (the shape of most controllers; each kernel holds one tile and has the
-// registers of the standalone kernel), and one holding every other tile.
+// Kernels of the batched rollout, per model: one persistent kernel per tile
+// size and tile kind, each holding the one tile the standalone kernel of that
+// shape holds (a kernel holding many tiles has the registers of the largest
+// and spills).  Kinds: the layout form of the paper's bodies, the runtime-P
+// form and the indicator tile, each without and with a costmap.
 constexpr int kTileSizes = 5;       // S = 16, 32, 64, 128, 256
-constexpr int kBatchKeys = kTileSizes + 1;
+constexpr int kTileKinds = 6;
+constexpr int kBatchKeys = kTileSizes * kTileKinds;
 constexpr int kBatchGroups = kModels * kBatchKeys;
 
 // The rollout units of a batched launch, grouped by kernel: one persistent
-// launch per group present (a kernel that holds many tiles needs more
-// registers and runs each of them slower).  Group g (model g / kBatchKeys,
-// kernel g % kBatchKeys) is units [begin[g], begin[g] + count[g]) of the
-// list, longest first; lds[g] is the dynamic LDS its kernel needs and
+// launch per group present.  Group g (model g / kBatchKeys, kernel
+// g % kBatchKeys) is units [begin[g], begin[g] + count[g]) of the list,
+// longest first; lds[g] is the dynamic LDS its kernel needs and
 // work[g] the sum of its units' estimates.  The queue of group g is words
 // 2g and 2g + 1.
 struct UnitGroups {
@@ -327,8 +328,8 @@ inline size_t tile_lds_bytes(int J, int T, int n, int S)
 // Kernel launchers (mppi_kernels.hip).  The rollout kernels of each model
 // live in their own unit (mppi_rollout_<model>.hip).
 using BatchRolloutKernel = void (*)(const DevParams*, const BatchUnit*, int, const BatchIn*, uint32_t*);
-// The batched rollout kernel of `key` (0..kTileSizes-1: the layout-form tile
-// of S = 16 << key; kTileSizes: every other tile) of each model.
+// The batched rollout kernel of `key` (kind key / kTileSizes, tile size
+// 16 << key % kTileSizes) of each model.
 hipError_t launch_rollout_quad6(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_rollout_quad5(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_rollout_car(const DevParams& p, const StepArgs& a, size_t lds, hipStream_t s);

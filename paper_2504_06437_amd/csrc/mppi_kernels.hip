@@ -444,13 +444,15 @@ hipError_t launch_philox_words(const DevParams& p, uint64_t counter, uint32_t* d
 
 int batch_group(const DevParams& p)
 {
-    int key = kTileSizes;
-    if (p.cost_mode != MPPI_COST_INDICATOR && p.sdf == nullptr && p.P == fixed_points(p.model) &&
-        p.shape_kind != kShapeGeneral) {
-        for (int k = 0; k < kTileSizes; ++k)
-            if (p.spt == (16 << k)) key = k;
-    }
-    return p.model * kBatchKeys + key;
+    int size = 0;
+    for (int k = 0; k < kTileSizes; ++k)
+        if (p.spt == (16 << k)) size = k;
+    const int map = p.sdf != nullptr;
+    int kind;
+    if (p.cost_mode == MPPI_COST_INDICATOR) kind = 4 + map;
+    else if (p.P == fixed_points(p.model) && p.shape_kind != kShapeGeneral) kind = map;
+    else kind = 2 + map;
+    return p.model * kBatchKeys + kind * kTileSizes + size;
 }
 
 int batch_rollout_blocks_per_cu(int group, size_t lds)

@@ -1,5 +1,5 @@
 // Rollout kernels of the quad5 model (the standalone tile kernels and the
-// batched persistent kernel), compiled in a unit of their own.
+// batched persistent kernels), compiled in a unit of their own.
 #include "mppi_device.hpp"
 
 namespace dbas {
@@ -9,16 +9,6 @@ hipError_t launch_rollout_quad5(const DevParams& p, const StepArgs& a, size_t ld
     return launch_rollout_m<MPPI_QUAD5>(p, a, lds, s);
 }
 
-BatchRolloutKernel batch_rollout_kernel_quad5(int key)
-{
-    switch (key) {
-    case 0: return k_batch_rollout_layout<MPPI_QUAD5, 16>;
-    case 1: return k_batch_rollout_layout<MPPI_QUAD5, 32>;
-    case 2: return k_batch_rollout_layout<MPPI_QUAD5, 64>;
-    case 3: return k_batch_rollout_layout<MPPI_QUAD5, 128>;
-    case 4: return k_batch_rollout_layout<MPPI_QUAD5, 256>;
-    default: return k_batch_rollout<MPPI_QUAD5>;
-    }
-}
+BatchRolloutKernel batch_rollout_kernel_quad5(int key) { return batch_kernel_of<MPPI_QUAD5>(key); }
 
 }  // namespace dbas
