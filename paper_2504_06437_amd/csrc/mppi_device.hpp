@@ -398,7 +398,7 @@ struct TileLds {
     double* e;        // [kMaxTile] tile exponentials
     double* slots;    // [16] block-reduction slots
     int* work;        // [4] pool waves per SIMD, [4] the owner wave's SIMD,
-                      // [5], [6] the batched kernel's unit counters, [7] the bits of
+                      // [5], [6] unused, [7] the bits of
                       // the largest |o|^2 over the obstacles
     // chunk slots, two buffers each (buffer b at offset b * cb, cb = cs + kXSlots):
     float4* in;       // [2][cs] per (step, sample): (f0, f1, control cost, costmap terms of the
@@ -489,7 +489,7 @@ __device__ __forceinline__ float2 block_sum_f2(float2 v, double* slots)
 // The runtime-P tile takes any shape: h = (|e|^2 - r^2) + 2 e.d_i + |d_i|^2
 // with d_i the rotated offset, one add and two FMAs a pair.
 // (sa2, sb2) = 2 (a_i, b_i), ss = a_i^2 + b_i^2.
-template <int MODEL, int PT, bool GROUPED>
+template <int MODEL, int PT>
 __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const TileLds& L, int P, const float* sa2,
                                                     const float* sb2, const float* ss, float4 pose, int sp, int lg,
                                                     float omax2)
@@ -536,11 +536,6 @@ __device__ __forceinline__ float fused_barrier_pose(const DevParams& p, const Ti
             }
             sum += f;
         };
-        // (the batched kernel, short of registers, keeps a test per obstacle)
-        if constexpr (!GROUPED) {
-            run(one);
-            return;
-        }
         const float4* ob = L.obs + sp;
         int i = 0;
         for (; i + 4 <= q; i += 4) {
@@ -790,9 +785,8 @@ __device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLd
 // ---------------------------------------------------------------------------
 // One tile of S samples: rollout and the tile's softmax partials.
 // PT = compile-time number of shape points (0: runtime P <= MPPI_PMAX; the
-// fixed-P tiles use the layout form of the paper's bodies).  SC: share the
-// barrier units out by SIMD (the standalone kernel) rather than from one LDS
-// counter (the batched kernel); see barrier_chunk.
+// fixed-P tiles use the layout form of the paper's bodies).  The standalone
+// and the batched kernels run the same tile.
 //
 // The horizon is cut into chunks of tc steps that flow through a pipeline of
 // workgroup-wide stages.  In stage k:
@@ -800,16 +794,15 @@ __device__ __forceinline__ float clearance_pose(const DevParams& p, const TileLd
 //     recursion over chunk k-2 and then integrate the dynamics of chunk k --
 //     the two sequential parts, one lane per sample;
 //   * the other waves draw the noise and inputs of chunk k+1;
-//   * then the pool waves take units of the fused-barrier work of chunk k-1
-//     (with the LDS counter, the owner waves join when their sequential part
-//     is done).
+//   * then the pool waves take units of the fused-barrier work of chunk k-1,
+//     shared out by SIMD (see barrier_chunk).
 // Every (step, sample) of a chunk is split over nsp adjacent lanes; lane sp
 // of the group takes obstacles sp, sp + nsp, ..., so a wave's lanes read one
 // contiguous run of obstacles at a time; the nsp partial sums meet by wave
 // shuffles.
 // Inputs, poses and barrier values are double-buffered by chunk parity.
 // ---------------------------------------------------------------------------
-template <int MODEL, int S, int PT, bool SC, bool IND, bool MAP>
+template <int MODEL, int S, int PT, bool IND, bool MAP>
 __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, unsigned char* smem)
 {
     static_assert(!IND || PT == 0, "the indicator runs on the runtime-P tile");
@@ -891,20 +884,18 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     }
     lds_barrier();
 
-    // With SC the barrier units of a stage are shared out by SIMD (see
+    // The barrier units of a stage are shared out by SIMD (see
     // barrier_chunk): each wave learns its SIMD and, outside the owner waves,
     // its slot among the pool waves of that SIMD.
-    [[maybe_unused]] const int simd = SC ? __builtin_amdgcn_s_getreg(kHwIdSimd) : 0;
+    const int simd = __builtin_amdgcn_s_getreg(kHwIdSimd);
     int pslot = 0;
-    if constexpr (SC) {
-        if (lane == 0) {
-            if (wave >= DW) pslot = atomicAdd(&L.work[simd], 1);
-            else if (wave == 0) L.work[4] = simd;
-        }
-        pslot = __builtin_amdgcn_readfirstlane(pslot);
+    if (lane == 0) {
+        if (wave >= DW) pslot = atomicAdd(&L.work[simd], 1);
+        else if (wave == 0) L.work[4] = simd;
     }
-    [[maybe_unused]] int my_pool = 1;                   // pool waves on this wave's SIMD
-    [[maybe_unused]] int my_classes = 0;                // bit cl: this wave's SIMD serves unit class cl
+    pslot = __builtin_amdgcn_readfirstlane(pslot);
+    int my_pool = 1;                    // pool waves on this wave's SIMD
+    int my_classes = 0;                 // bit cl: this wave's SIMD serves unit class cl
 
     float beta0 = 0.0f, beta_d = 0.0f;      // fused B(h(x0)), fused B(h(x_d)), formed in stage 1
 
@@ -1040,17 +1031,15 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     const int lg_pack = (p.lg_pack & kLgPackSet) ? p.lg_pack : tile_lg_pack(J, T, NS, S, P);
 
     // Fused barrier of every (step, sample) of chunk c, in units of one wave.
-    // With SC the units are shared out by SIMD, not taken first come first
-    // served: a SIMD's older waves win the issue arbitration, so under a
+    // The units are shared out by SIMD, not taken first come first served: a SIMD's older waves win the issue arbitration, so under a
     // shared counter they took the most units and the SIMD of the owner wave
     // finished last.  Unit u belongs to class u mod 4; class cl is served by
     // the SIMD of rank 3 - cl from the owner wave's SIMD (the class that is
     // one unit short, when there is one, goes to the owner's SIMD), or,
     // should that SIMD have no pool wave, by the next one that has.  Within a
     // SIMD the pool waves take the class's units round-robin by slot; the
-    // owner waves take none.  Without SC (the general batched kernel, where
-    // the extra state costs registers) every wave takes units from an LDS
-    // counter.  Which wave computes a unit never changes its arithmetic.
+    // owner waves take none.  Which wave computes a unit never changes its
+    // arithmetic.
     auto barrier_chunk = [&](int c) __attribute__((always_inline)) {
         const int items = chunk_len(c) * S;
         // with the barrier state, chunk 0 also takes the poses of x0 and x_d
@@ -1083,27 +1072,16 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
                 for (int m = 1; m < nsp; m <<= 1) part = fminf(part, __shfl_xor(part, m));
                 if (sp == 0 && item < items) bv[item] = part;
             } else {
-                if (item < all) part = fused_barrier_pose<MODEL, PT, SC>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, omax2);
+                if (item < all) part = fused_barrier_pose<MODEL, PT>(p, L, P, sa2, sb2, ss, pz[item], sp, lg, omax2);
                 for (int m = 1; m < nsp; m <<= 1) part += __shfl_xor(part, m);
                 if (sp == 0 && item < all) bv[item] = part;
             }
         };
-        if constexpr (SC) {
-            if (wave < DW) return;
-            // the classes this SIMD serves, in turn (one copy of the unit code)
-            for (int cls = my_classes; cls != 0; cls &= cls - 1) {
-                const int cl = __builtin_ctz(cls);
-                for (int u = cl + kSimdsPerCU * pslot; u < units; u += kSimdsPerCU * my_pool) unit(u);
-            }
-        } else {
-            int* counter = &L.work[5 + ((c + 1) & 1)];
-            for (;;) {
-                int u = 0;
-                if (lane == 0) u = atomicAdd(counter, 1);
-                u = __shfl(u, 0);
-                if (u >= units) break;
-                unit(u);
-            }
+        if (wave < DW) return;
+        // the classes this SIMD serves, in turn (one copy of the unit code)
+        for (int cls = my_classes; cls != 0; cls &= cls - 1) {
+            const int cl = __builtin_ctz(cls);
+            for (int u = cl + kSimdsPerCU * pslot; u < units; u += kSimdsPerCU * my_pool) unit(u);
         }
     };
 
@@ -1124,7 +1102,7 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
     lds_barrier();
     if constexpr (PT != 0) omax2 = 2.0f * __int_as_float(L.work[7]);
     // (the SIMD counts are final: the barriers since have synchronised)
-    if constexpr (SC) {
+    {
         my_pool = __builtin_amdgcn_readfirstlane(max(L.work[simd], 1));
         const int osimd = __builtin_amdgcn_readfirstlane(L.work[4]);
         int mine = 0;
@@ -1137,9 +1115,6 @@ __device__ void rollout_tile(const DevParams& p, const int tile, const X0& xs, u
         my_classes = __builtin_amdgcn_readfirstlane(mine);
     }
     for (int st_k = 0; st_k <= nch + 1; ++st_k) {
-        if constexpr (!SC) {
-            if (tid == 0) L.work[5 + ((st_k + 1) & 1)] = 0;      // counter of the next stage
-        }
         if (wave < DW) {
             if (!IND && owner && st_k == 2) {
                 // beta_0 and beta_d, formed in stage 1 in chunk 0's extra
@@ -1389,7 +1364,7 @@ __global__ __launch_bounds__(kRollBlock) void k_rollout(DevParams p, StepArgs a)
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = a.x0[i];
     }
     xs.parity = a.parity;
-    rollout_tile<MODEL, S, PT, true, IND, MAP>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
+    rollout_tile<MODEL, S, PT, IND, MAP>(p, xcd_tile((int)blockIdx.x, p.tiles), xs, smem);
 }
 
 // Persistent rollout over a work list of (controller, tile) units of one
@@ -1415,7 +1390,7 @@ __global__ __launch_bounds__(kRollBlock) void k_batch_rollout(const DevParams* _
 #pragma unroll
         for (int i = 0; i < MPPI_NMAX + 2; ++i) xs.v[i] = in[bu.ctrl].x0[i];
         xs.parity = in[bu.ctrl].parity;
-        rollout_tile<MODEL, S, PT, true, IND, MAP>(p, bu.tile, xs, smem);
+        rollout_tile<MODEL, S, PT, IND, MAP>(p, bu.tile, xs, smem);
         __syncthreads();
     }
     if (threadIdx.x == 0) {

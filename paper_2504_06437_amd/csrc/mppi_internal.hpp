@@ -225,7 +225,7 @@ __host__ __device__ inline size_t tile_fixed_lds(int J, int T, int n)
     b = (b + 15) & ~(size_t)15;
     b += (size_t)kMaxTile * 8;                  // tile exponentials
     b += 16 * 8;                                // block-reduction slots
-    b += 64;                                    // pool waves per SIMD, owner SIMD, unit counters
+    b += 64;                                    // pool waves per SIMD, owner SIMD, the largest |o|^2
     b += (size_t)kXSlots * kSlotBytes;          // two extra slots per chunk buffer (x0, x_d)
     return b;
 }
